@@ -1,0 +1,16 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line(
+        "markers", "gpu: needs an AMD Instinct GPU (gfx950) and the built HIP "
+        "library")
+    config.addinivalue_line(
+        "markers", "slow: long CPU test (still part of the default run)")
