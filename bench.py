@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput of the explicit finite-volume shallow-water step on one GPU.
+
+One "step" is one pass of the whole hot path over the mesh: the device-side
+time step (CFL min-reduction of the previous step), every edge's HLLC flux
+with hydrostatic reconstruction and bed-slope terms, boundary fluxes, the
+semi-implicit Manning friction, the conservative update with wet/dry
+handling, and the block minimum feeding the next step's time step. The
+default workload is the 13 M-cell synthetic river reach (inflow 500 m^3/s,
+fixed downstream stage, partly dry floodplain), FP64 throughout.
+
+Prints one JSON line: cell-updates/s over the timed steps (inputs resident
+in HBM), the roofline of the step kernel (algorithmic bytes per launch over
+the kernel's average duration, measured with HIP events on the stream the
+kernel runs on) and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--workload river|bumps|canal]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("cell-updates/s FP64 + HBM GB/s vs peak; ensemble and adjoint "
+          "cost vs plain")
+PEAK_HBM_GBS = 8000.0           # MI355X HBM3E, published
+# Algorithmic bytes the method moves per cell-update (FP64 state in and
+# out, per-cell bed / friction / 1/area / inscribed radius, ~1.5 edges of
+# geometry and connectivity, per-cell edge slots); derivation in the design doc.
+ALG_BYTES_PER_CELL = 140
+KERNEL_SRC = os.path.join(ROOT, "paper_2010_14416_amd", "csrc",
+                          "swe_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def make_case(args):
+    import workloads as W
+    if args.workload == "river":
+        return W.river(n_target=args.cells, workers=args.workers), (
+            f"river-{args.cells / 1e6:g}M: seeded meandering reach, "
+            "jittered-point Delaunay mesh, thalweg + Perlin bed, Manning "
+            "U[0.02,0.05], inflow 500 m^3/s, fixed outlet stage, partly dry "
+            "floodplain")
+    if args.workload == "bumps":
+        return W.bumps_canal(), ("bumps-canal-1M: 1000x500 squares, dam break "
+                                 "onto a dry bed over 20 Gaussian bumps, "
+                                 "Manning 0.03")
+    return W.dam_break_canal(), "dam-break-canal-4k: 100x20 squares"
+
+
+def traffic_per_launch(workload_name, n_cells):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, if it was taken on this kernel source and workload size."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha256") != kernel_hash() or \
+            t.get("n_cells") != n_cells:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(case, seconds, threads):
+    import oracle
+    o = oracle.Oracle(case, threads=threads)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.run(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 200:
+            break
+    return dict(value=case.n_cells * steps / el, unit="cell-updates/s",
+                cores=threads, kind="oracle",
+                sample=f"{steps} oracle steps from the initial state of the "
+                       f"same {case.n_cells}-cell workload ({el:.1f} s, "
+                       f"setup excluded)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="river",
+                    choices=["river", "bumps", "canal"])
+    ap.add_argument("--cells", type=int, default=13_000_000)
+    ap.add_argument("--block-cells", type=int, default=256)
+    ap.add_argument("--workers", type=int,
+                    default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build's hot path has no "
+              f"multi-GPU decomposition (asked for --gpus {args.gpus}).",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_2010_14416_amd import Solver
+
+    t0 = time.perf_counter()
+    case, desc = make_case(args)
+    log(f"workload {case.name}: {case.n_cells} cells "
+        f"({time.perf_counter() - t0:.1f} s to generate)")
+    t0 = time.perf_counter()
+    s = Solver(case, device=0, block_cells=args.block_cells)
+    info = s.info()
+    s.advance(1, want_time=True)          # device set-up + first step
+    setup_s = time.perf_counter() - t0
+    log(f"set-up {setup_s:.1f} s, {info['n_blocks']} blocks, "
+        f"{info['n_block_edges']} block edges")
+    s.advance(args.warmup, want_time=True)
+    stream = s.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    s.advance(args.steps)                 # enqueue only; no host sync
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    elapsed_ms = ev0.elapsed_time(ev1)
+    t_sim, last_dt, step = s.time()       # also raises on a numeric fault
+    log(f"{args.steps} steps in {elapsed_ms:.2f} ms; t = {t_sim:.4f} s, "
+        f"dt = {last_dt:.4g} s")
+
+    n = case.n_cells
+    ms_per_step = elapsed_ms / args.steps
+    value = n * args.steps / (elapsed_ms * 1e-3)
+    alg_bytes = ALG_BYTES_PER_CELL * n
+    achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS,
+                    unit="GB/s", frac=achieved / PEAK_HBM_GBS,
+                    traffic=traffic_per_launch(case.name, n))
+
+    base = None
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", 0) or
+                      (os.cpu_count() or 1))
+        log(f"cpu baseline: oracle on {threads} threads")
+        base = cpu_baseline(case, args.cpu_seconds, threads)
+        log(f"cpu baseline {base['value']:.3e} cell-updates/s")
+
+    out = dict(
+        metric=METRIC, value=value, unit="cell-updates/s", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=ms_per_step,
+        higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload=desc, n_cells=n, n_edges=info["n_edges"],
+                    block_cells=info["block_cells"], setup_s=round(setup_s, 2),
+                    effective_gbs=achieved),
+        roofline=roofline, cpu_baseline=base)
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * swe.h -- C interface of the explicit finite-volume shallow-water step on
+ * unstructured triangles for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Delmas & Soulaimani, "Multi-GPU implementation of a time-explicit
+ * finite volume solver for the Shallow-Water Equations using CUDA and a
+ * CUDA-Aware version of OpenMPI", arXiv 2010.14416. The conserved state is
+ * U = (h, hu, hv) per triangle (eq. 1, cell averages of eq. 7); each step
+ * evaluates the HLLC flux of every edge on hydrostatically reconstructed
+ * states (sec. 3.2, eqs. 17-26 and 28), the bed-slope term (eq. 30), the
+ * semi-implicit Manning friction (eqs. 31-36), the explicit update (eq. 37)
+ * and the CFL time step (eq. 15 with the inscribed radius, sec. 3.1), all on
+ * the device.
+ *
+ * Conventions
+ *  - Every call returns a swe_status; swe_last_error() gives a message. No
+ *    exception crosses the interface.
+ *  - Input pointers are caller-owned and copied during the call; nothing is
+ *    retained. Outputs are written into caller-allocated arrays.
+ *  - Per-cell arrays follow the caller's triangle order ("user order"). The
+ *    library reorders cells internally for locality; that order is invisible
+ *    except through swe_get_cell_order().
+ *  - SI units. Node and cell indices are 0-based int32.
+ *  - A context is not thread-safe; several contexts may coexist.
+ *  - Host-side validation (mesh, fields, state, parameters) needs no GPU;
+ *    device memory is set up on first use (swe_advance, swe_get_state,
+ *    device-pointer inputs, swe_get_diagnostics).
+ */
+#ifndef SWE_H
+#define SWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWE_ABI_VERSION 1
+#define SWE_MAX_TAG 1024
+
+typedef struct swe_ctx swe_ctx;
+
+typedef enum {
+    SWE_OK = 0,
+    SWE_EINVAL = -1,     /* bad argument (null pointer, size, parameter)   */
+    SWE_EMESH = -2,      /* invalid mesh (degenerate, non-manifold, ...)    */
+    SWE_ESTATE = -3,     /* invalid field or state (NaN, h < 0, n < 0)      */
+    SWE_EDEVICE = -4,    /* HIP runtime error or no usable device           */
+    SWE_ENOMEM = -5,     /* host or device allocation failed / workspace    */
+    SWE_ENOTREADY = -6,  /* call out of order (e.g. no mesh yet)            */
+    SWE_ENUMERIC = -7    /* non-finite state or unbounded time step         */
+} swe_status;
+
+/* Boundary-condition kinds (sec. 3.1). WALL, TRANSMISSIVE and INFLOW are
+ * the paper's three kinds; FIXED_DEPTH and FIXED_STAGE hold a downstream
+ * water level and are additions (a ghost state of the given depth, or of
+ * depth max(0, stage - z_i), with the cell's velocity, through HLLC). */
+typedef enum {
+    SWE_BC_WALL = 0,          /* value ignored                                */
+    SWE_BC_TRANSMISSIVE = 1,  /* value ignored                                */
+    SWE_BC_INFLOW = 2,        /* value = total discharge Q of the tag [m^3/s],
+                                 spread uniformly over the tag's edge length */
+    SWE_BC_FIXED_DEPTH = 3,   /* value = ghost depth [m], >= 0                */
+    SWE_BC_FIXED_STAGE = 4    /* value = ghost water-surface elevation [m]    */
+} swe_bc_kind;
+
+typedef enum { SWE_MEM_HOST = 0, SWE_MEM_DEVICE = 1 } swe_mem;
+
+typedef struct {
+    double g;              /* gravity [m/s^2] > 0 (9.81)                       */
+    double cfl;            /* CFL number of eq. 15, > 0 (0.9, sec. 3.1)        */
+    double h_dry;          /* wet/dry depth threshold [m] >= 0 (1e-6)          */
+    double dt_max;         /* upper bound on the time step [s] > 0 (+inf)      */
+    int32_t check_every;   /* steps between host polls of the device clock
+                              when t_end is finite (64)                       */
+    int32_t block_cells;   /* cells per mesh block, 64..1024, a multiple of
+                              64 (256); takes effect at the next set_mesh    */
+    int32_t reorder;       /* 1: space-filling-curve cell order (default);
+                              0: keep the user order; next set_mesh           */
+    int32_t reserved;      /* must be 0                                       */
+} swe_params;
+
+typedef struct {
+    int64_t n_nodes, n_cells, n_edges, n_boundary_edges;
+    int64_t n_blocks;          /* mesh blocks of block_cells cells           */
+    int64_t n_block_edges;     /* edge records over all blocks (edges on a
+                                  block border appear in both blocks)        */
+    int32_t block_cells, max_block_edges;
+    double min_inradius;       /* smallest inscribed radius [m]              */
+    double total_area;         /* sum of cell areas [m^2]                    */
+} swe_mesh_stats;
+
+/* Version of this interface (SWE_ABI_VERSION). */
+int swe_abi_version(void);
+
+/* Fills *p with the defaults listed in swe_params. */
+swe_status swe_default_params(swe_params *p);
+
+/* Creates a context bound to HIP device `device` (an ordinal). No device
+ * call is made here. *out is owned by the caller and released with
+ * swe_destroy. */
+swe_status swe_create(swe_ctx **out, int device);
+
+/* Releases the context and every device allocation it made (a workspace
+ * bound with swe_bind_workspace stays the caller's). NULL is a no-op. */
+void swe_destroy(swe_ctx *ctx);
+
+/* Message of the last failing call on ctx (or of swe_create when ctx is
+ * NULL); valid until the next call on ctx. */
+const char *swe_last_error(const swe_ctx *ctx);
+
+/* HIP stream (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream)
+ * on which every later kernel and copy is issued; NULL = the null stream.
+ * The stream must belong to the context's device and outlive its use. */
+swe_status swe_set_stream(swe_ctx *ctx, void *hip_stream);
+
+/* Validates and stores parameters. g, cfl, h_dry, dt_max apply from the
+ * next step; block_cells and reorder from the next swe_set_mesh. */
+swe_status swe_set_params(swe_ctx *ctx, const swe_params *p);
+swe_status swe_get_params(const swe_ctx *ctx, swe_params *p);
+
+/* Mesh (sec. 3.1): n_nodes nodes with coordinates xy[2*k], xy[2*k+1];
+ * n_cells triangles tri[3*c..3*c+2] in either orientation (a clockwise
+ * triangle is reoriented by exchanging its second and third vertex). The
+ * boundary condition of a boundary edge is chosen by a tag: n_bnd segments
+ * bnd_nodes[2*s], bnd_nodes[2*s+1] (either order) with tag bnd_tag[s] in
+ * [0, SWE_MAX_TAG); boundary edges not listed carry tag 0. n_bnd may be 0
+ * (bnd_nodes, bnd_tag then may be NULL).
+ * Errors: SWE_EMESH for a node index out of range, a repeated vertex, a
+ * zero-area triangle, an edge shared by more than two triangles, two
+ * triangles on the same side of an edge, a segment that is not a boundary
+ * edge or is listed twice, a tag out of range, a non-finite coordinate.
+ * Resets the bathymetry and Manning field to 0, the state to dry, the clock
+ * to t = 0 and drops any bound workspace. */
+swe_status swe_set_mesh(swe_ctx *ctx, int64_t n_nodes, const double *xy,
+                        int64_t n_cells, const int32_t *tri, int64_t n_bnd,
+                        const int32_t *bnd_nodes, const int32_t *bnd_tag);
+
+/* Counts and sizes of the current mesh. */
+swe_status swe_mesh_info(const swe_ctx *ctx, swe_mesh_stats *out);
+
+/* internal_of_user[c] = position of user cell c in the library's internal
+ * (locality) order. */
+swe_status swe_get_cell_order(const swe_ctx *ctx, int32_t *internal_of_user);
+
+/* Cell areas |Omega_i| and inscribed radii R_i (sec. 3.1), user order. */
+swe_status swe_get_geometry(const swe_ctx *ctx, double *area,
+                            double *inradius);
+
+/* Boundary condition of all boundary edges carrying `tag` (sec. 3.1). Every
+ * tag starts as SWE_BC_WALL. */
+swe_status swe_set_bc(swe_ctx *ctx, int32_t tag, swe_bc_kind kind,
+                      double value);
+
+/* Bed elevation z (eq. 4, the b of the paper) per cell [m], finite. */
+swe_status swe_set_bathymetry(swe_ctx *ctx, const double *z, swe_mem mem);
+
+/* Manning coefficient m per cell (eq. 5) [s m^-1/3], finite and >= 0. */
+swe_status swe_set_manning(swe_ctx *ctx, const double *n, swe_mem mem);
+
+/* State U = (h, hu, hv) per cell; h >= 0, all finite (SWE_ESTATE otherwise;
+ * device inputs are checked on the device). Invalidates the pending time
+ * step, which is recomputed from this state. */
+swe_status swe_set_state(swe_ctx *ctx, const double *h, const double *hu,
+                         const double *hv, swe_mem mem);
+
+/* Copies the current state out (user order) and synchronises the stream. */
+swe_status swe_get_state(swe_ctx *ctx, double *h, double *hu, double *hv,
+                         swe_mem mem);
+
+/* Simulated time and step counter, for resuming a run. */
+swe_status swe_set_time(swe_ctx *ctx, double t, int64_t step);
+swe_status swe_get_time(swe_ctx *ctx, double *t, double *last_dt,
+                        int64_t *step);
+
+/* Advances at most max_steps explicit steps, stopping early when the time
+ * reaches t_end (the last step is shortened to land on t_end exactly; pass
+ * INFINITY to run exactly max_steps). The time step of each step is
+ * CFL * min over wet cells of R_i / (sqrt(g h_i) + |V_i|), bounded by
+ * dt_max, computed on the device from the state the step starts from.
+ * With t_end = INFINITY the call only enqueues work (no host sync);
+ * otherwise the host polls the device clock every check_every steps.
+ * *steps_done and *t_now (either may be NULL) are exact after a sync; with
+ * t_end = INFINITY they are max_steps and a synchronised time. Returns
+ * SWE_ENUMERIC if a step produced a non-finite state or an unbounded time
+ * step (all cells dry, dt_max and t_end infinite). */
+swe_status swe_advance(swe_ctx *ctx, int64_t max_steps, double t_end,
+                       int64_t *steps_done, double *t_now);
+
+/* Total water volume sum |Omega_i| h_i [m^3], the volume added by the
+ * positivity fix since the mesh was set [m^3], and the number of cells
+ * with h > h_dry. Synchronises the stream. */
+swe_status swe_get_diagnostics(swe_ctx *ctx, double *mass, double *ledger,
+                               int64_t *n_wet);
+
+/* Device memory: by default the library allocates it on first use. A
+ * caller that owns device memory (e.g. a torch uint8 tensor) can instead
+ * bind a workspace of at least swe_workspace_bytes() bytes, 256-byte
+ * aligned, after swe_set_mesh and before the first device use; it must
+ * stay alive until the next swe_set_mesh or swe_destroy. */
+swe_status swe_workspace_bytes(const swe_ctx *ctx, size_t *bytes);
+swe_status swe_bind_workspace(swe_ctx *ctx, void *dev_ptr, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWE_H */

@@ -1,0 +1,797 @@
+// C interface (include/swe.h) of the shallow-water step: context, input
+// validation and reordering on the host, device memory, the step loop.
+#include "../../include/swe.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "swe_device.hpp"
+#include "swe_mesh.hpp"
+
+using swe::BcEntry;
+using swe::BlockMesh;
+using swe::Clock;
+
+namespace {
+
+// Device buffers, carved from one workspace (256-byte aligned pieces).
+struct DevBufs {
+    double *h[2], *hu[2], *hv[2];
+    double *z, *man, *gm2, *inv_area, *area, *inr;
+    uint64_t *slots;
+    int32_t *internal_of_user, *user_of_internal;
+    int32_t *blk_cell, *blk_edge;
+    int32_t *be_left, *be_right;
+    double *be_nx, *be_ny, *be_len;
+    BcEntry *bc;
+    Clock *clock;
+    double *ledger;
+    double *part_mass;
+    unsigned long long *part_wet;
+    unsigned *flag;
+};
+
+constexpr int kDiagParts = 1024;
+
+}  // namespace
+
+struct swe_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    swe_params params{};
+    std::string err;
+    bool has_mesh = false;
+    BlockMesh mesh;
+    // host copies in internal order; *_dirty: newer than the device copy
+    std::vector<double> z, man, h, hu, hv;
+    bool z_dirty = false, man_dirty = false, state_dirty = false;
+    bool gm2_dirty = true;
+    std::vector<BcEntry> bc;
+    bool bc_dirty = true;
+    // device
+    bool dev_ready = false;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    DevBufs d{};
+    int cur_buf = 0;           // ping-pong buffer holding the current state
+    int cur_slot = 0;          // clock slot read by the next step
+    bool dt_valid = false;     // clock slot cur_slot holds min R/s of state
+    bool clock_dirty = true;   // host t/step must be pushed to the device
+    double t_host = 0.0;       // valid when t_known
+    bool t_known = true;
+    int64_t step_host = 0;
+    double last_dt_host = 0.0;
+    long long step_index = 0;  // steps launched since the mesh was set
+    bool uploaded = false;     // host memory queued on the stream
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+swe_status fail(swe_ctx *c, swe_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+swe_status hip_fail(swe_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, SWE_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call)                                                  \
+    do {                                                                   \
+        hipError_t e_ = (call);                                            \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);           \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace layout: returns the total size; fills d when base != nullptr.
+size_t layout(const BlockMesh &m, char *base, DevBufs *d)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    const size_t nc = size_t(m.n_cells), nb = size_t(m.n_blocks);
+    const size_t nbe = m.be_left.size();
+    DevBufs t{};
+    for (int k = 0; k < 2; ++k) {
+        t.h[k] = (double *)take(nc * 8);
+        t.hu[k] = (double *)take(nc * 8);
+        t.hv[k] = (double *)take(nc * 8);
+    }
+    t.z = (double *)take(nc * 8);
+    t.man = (double *)take(nc * 8);
+    t.gm2 = (double *)take(nc * 8);
+    t.inv_area = (double *)take(nc * 8);
+    t.area = (double *)take(nc * 8);
+    t.inr = (double *)take(nc * 8);
+    t.slots = (uint64_t *)take(nc * 8);
+    t.internal_of_user = (int32_t *)take(nc * 4);
+    t.user_of_internal = (int32_t *)take(nc * 4);
+    t.blk_cell = (int32_t *)take((nb + 1) * 4);
+    t.blk_edge = (int32_t *)take((nb + 1) * 4);
+    t.be_left = (int32_t *)take(nbe * 4);
+    t.be_right = (int32_t *)take(nbe * 4);
+    t.be_nx = (double *)take(nbe * 8);
+    t.be_ny = (double *)take(nbe * 8);
+    t.be_len = (double *)take(nbe * 8);
+    t.bc = (BcEntry *)take(sizeof(BcEntry) * SWE_MAX_TAG);
+    t.clock = (Clock *)take(sizeof(Clock));
+    t.ledger = (double *)take(nb * 8);
+    t.part_mass = (double *)take(kDiagParts * 8);
+    t.part_wet = (unsigned long long *)take(kDiagParts * 8);
+    t.flag = (unsigned *)take(256);
+    if (d) *d = t;
+    return off;
+}
+
+bool valid_block_cells(int32_t b)
+{
+    return b == 64 || b == 128 || b == 256 || b == 512;
+}
+
+swe_status require_mesh(swe_ctx *c)
+{
+    if (!c) return SWE_EINVAL;
+    if (!c->has_mesh) return fail(c, SWE_ENOTREADY, "no mesh set");
+    return SWE_OK;
+}
+
+template <typename T>
+swe_status upload(swe_ctx *c, T *dst, const T *src, size_t n)
+{
+    if (n == 0) return SWE_OK;
+    HIPCHK(c, hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice,
+                             c->stream));
+    c->uploaded = true;
+    return SWE_OK;
+}
+
+// Allocates (or adopts) the workspace and uploads whatever the host holds
+// newer than the device.
+swe_status prepare(swe_ctx *c)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    HIPCHK(c, hipSetDevice(c->device));
+    const BlockMesh &m = c->mesh;
+    const size_t nc = size_t(m.n_cells);
+    if (!c->dev_ready) {
+        const size_t need = layout(m, nullptr, nullptr);
+        if (!c->ws) {
+            void *p = nullptr;
+            hipError_t e = hipMalloc(&p, need);
+            if (e != hipSuccess)
+                return fail(c, SWE_ENOMEM,
+                            std::string("device allocation of ") +
+                                std::to_string(need) + " bytes failed: " +
+                                hipGetErrorString(e));
+            c->ws = p;
+            c->ws_bytes = need;
+            c->ws_owned = true;
+        }
+        layout(m, (char *)c->ws, &c->d);
+        DevBufs &d = c->d;
+        if ((st = upload(c, d.inv_area, m.inv_area.data(), nc))) return st;
+        if ((st = upload(c, d.area, m.area.data(), nc))) return st;
+        if ((st = upload(c, d.inr, m.inradius.data(), nc))) return st;
+        if ((st = upload(c, d.slots, (const uint64_t *)m.slots.data(), nc)))
+            return st;
+        if ((st = upload(c, d.internal_of_user, m.internal_of_user.data(), nc)))
+            return st;
+        if ((st = upload(c, d.user_of_internal, m.user_of_internal.data(), nc)))
+            return st;
+        if ((st = upload(c, d.blk_cell, m.blk_cell.data(), m.blk_cell.size())))
+            return st;
+        if ((st = upload(c, d.blk_edge, m.blk_edge.data(), m.blk_edge.size())))
+            return st;
+        const size_t nbe = m.be_left.size();
+        if ((st = upload(c, d.be_left, m.be_left.data(), nbe))) return st;
+        if ((st = upload(c, d.be_right, m.be_right.data(), nbe))) return st;
+        if ((st = upload(c, d.be_nx, m.be_nx.data(), nbe))) return st;
+        if ((st = upload(c, d.be_ny, m.be_ny.data(), nbe))) return st;
+        if ((st = upload(c, d.be_len, m.be_len.data(), nbe))) return st;
+        HIPCHK(c, swe::launch_fill_f64(d.ledger, 0.0, m.n_blocks, c->stream));
+        c->dev_ready = true;
+        c->z_dirty = c->man_dirty = c->state_dirty = true;
+        c->bc_dirty = c->gm2_dirty = c->clock_dirty = true;
+        c->dt_valid = false;
+        c->cur_buf = 0;
+        c->cur_slot = 0;
+    }
+    DevBufs &d = c->d;
+    if (c->z_dirty) {
+        if ((st = upload(c, d.z, c->z.data(), nc))) return st;
+        c->z_dirty = false;
+    }
+    if (c->man_dirty) {
+        if ((st = upload(c, d.man, c->man.data(), nc))) return st;
+        c->man_dirty = false;
+        c->gm2_dirty = true;
+    }
+    if (c->gm2_dirty) {
+        HIPCHK(c, swe::launch_gm2(d.man, d.gm2, nc, c->params.g, c->stream));
+        c->gm2_dirty = false;
+    }
+    if (c->state_dirty) {
+        if ((st = upload(c, d.h[c->cur_buf], c->h.data(), nc))) return st;
+        if ((st = upload(c, d.hu[c->cur_buf], c->hu.data(), nc))) return st;
+        if ((st = upload(c, d.hv[c->cur_buf], c->hv.data(), nc))) return st;
+        c->state_dirty = false;
+        c->dt_valid = false;
+    }
+    if (c->bc_dirty) {
+        // inflow discharge per unit length of each tag
+        for (int k = 0; k < SWE_MAX_TAG; ++k) {
+            BcEntry &b = c->bc[k];
+            const double L = c->mesh.tag_length[k];
+            b.q = (b.kind == SWE_BC_INFLOW && L > 0.0) ? b.value / L : 0.0;
+        }
+        if ((st = upload(c, d.bc, c->bc.data(), SWE_MAX_TAG))) return st;
+        c->bc_dirty = false;
+    }
+    if (c->clock_dirty) {
+        HIPCHK(c, swe::launch_clock_set(d.clock, c->t_host, c->step_host,
+                                        c->stream));
+        c->clock_dirty = false;
+        c->dt_valid = false;
+    }
+    if (!c->dt_valid) {
+        // min over wet cells of R_i / s_i of the current state, into the
+        // slot the next step reads
+        HIPCHK(c, swe::launch_slot_reset(d.clock, c->cur_slot, c->stream));
+        HIPCHK(c, swe::launch_min_rs(d.h[c->cur_buf], d.hu[c->cur_buf],
+                                     d.hv[c->cur_buf], d.inr, nc,
+                                     c->params.g, c->params.h_dry, d.clock,
+                                     c->cur_slot, c->stream));
+        c->dt_valid = true;
+    }
+    // host arrays were handed to the stream: wait before returning so the
+    // caller may free or reuse its inputs
+    if (c->uploaded) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->uploaded = false;
+    }
+    return SWE_OK;
+}
+
+swe_status read_clock(swe_ctx *c, Clock *out)
+{
+    HIPCHK(c, hipMemcpyAsync(out, c->d.clock, sizeof(Clock),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->t_host = out->t[c->cur_slot];
+    c->t_known = true;
+    c->step_host = out->steps;
+    c->last_dt_host = out->last_dt;
+    if (out->health) {
+        std::string why = (out->health & 1u) ? "non-finite state"
+                                             : "unbounded time step (no wet "
+                                               "cell, dt_max and t_end "
+                                               "infinite)";
+        return fail(c, SWE_ENUMERIC,
+                    why + " at step " + std::to_string(out->bad_step));
+    }
+    return SWE_OK;
+}
+
+swe_status check_flag(swe_ctx *c, bool *bad)
+{
+    unsigned f = 0;
+    HIPCHK(c, hipMemcpyAsync(&f, c->d.flag, sizeof f, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *bad = f != 0;
+    return SWE_OK;
+}
+
+enum class Field { z, manning };
+
+// Cell field given by the caller (user order) into the internal host copy,
+// or (device memory) straight into the device array.
+swe_status set_field(swe_ctx *c, const double *src, swe_mem mem, Field f)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    const bool nonneg = f == Field::manning;
+    const char *name = f == Field::z ? "bathymetry" : "manning";
+    std::vector<double> &host = f == Field::z ? c->z : c->man;
+    bool &dirty = f == Field::z ? c->z_dirty : c->man_dirty;
+    if (!src) return fail(c, SWE_EINVAL, std::string(name) + " is NULL");
+    const int64_t nc = c->mesh.n_cells;
+    if (mem == SWE_MEM_HOST) {
+        for (int64_t u = 0; u < nc; ++u)
+            if (!std::isfinite(src[u]) || (nonneg && !(src[u] >= 0.0)))
+                return fail(c, SWE_ESTATE,
+                            std::string(name) + " invalid at cell " +
+                                std::to_string(u));
+        for (int64_t i = 0; i < nc; ++i)
+            host[i] = src[c->mesh.user_of_internal[i]];
+        dirty = true;
+        if (f == Field::manning) c->gm2_dirty = true;
+        return SWE_OK;
+    }
+    if (mem != SWE_MEM_DEVICE) return fail(c, SWE_EINVAL, "bad memory kind");
+    if ((st = prepare(c))) return st;
+    double *dev = f == Field::z ? c->d.z : c->d.man;
+    HIPCHK(c, swe::launch_fill_u32(c->d.flag, 0u, 1, c->stream));
+    HIPCHK(c, swe::launch_check_field(src, nc, nonneg ? 1 : 0, c->d.flag,
+                                      c->stream));
+    bool bad = false;
+    if ((st = check_flag(c, &bad))) return st;
+    if (bad) return fail(c, SWE_ESTATE, std::string(name) + " invalid");
+    HIPCHK(c, swe::launch_gather1(src, dev, c->d.user_of_internal, nc,
+                                  c->stream));
+    if (f == Field::manning)
+        HIPCHK(c, swe::launch_gm2(c->d.man, c->d.gm2, nc, c->params.g,
+                                  c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SWE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_abi_version(void) { return SWE_ABI_VERSION; }
+
+swe_status swe_default_params(swe_params *p)
+{
+    if (!p) return SWE_EINVAL;
+    p->g = 9.81;
+    p->cfl = 0.9;
+    p->h_dry = 1e-6;
+    p->dt_max = INFINITY;
+    p->check_every = 64;
+    p->block_cells = 256;
+    p->reorder = 1;
+    p->reserved = 0;
+    return SWE_OK;
+}
+
+swe_status swe_create(swe_ctx **out, int device)
+{
+    if (!out) return SWE_EINVAL;
+    *out = nullptr;
+    if (device < 0) {
+        g_create_error = "negative device ordinal";
+        return SWE_EINVAL;
+    }
+    swe_ctx *c = new (std::nothrow) swe_ctx();
+    if (!c) {
+        g_create_error = "out of memory";
+        return SWE_ENOMEM;
+    }
+    c->device = device;
+    swe_default_params(&c->params);
+    c->bc.assign(SWE_MAX_TAG, BcEntry{SWE_BC_WALL, 0, 0.0, 0.0});
+    *out = c;
+    return SWE_OK;
+}
+
+void swe_destroy(swe_ctx *c)
+{
+    if (!c) return;
+    if (c->ws_owned && c->ws) {
+        (void)hipSetDevice(c->device);
+        (void)hipFree(c->ws);
+    }
+    delete c;
+}
+
+const char *swe_last_error(const swe_ctx *c)
+{
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+swe_status swe_set_stream(swe_ctx *c, void *stream)
+{
+    if (!c) return SWE_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return SWE_OK;
+}
+
+swe_status swe_set_params(swe_ctx *c, const swe_params *p)
+{
+    if (!c || !p) return SWE_EINVAL;
+    if (!(p->g > 0.0) || !std::isfinite(p->g))
+        return fail(c, SWE_EINVAL, "g must be positive and finite");
+    if (!(p->cfl > 0.0) || !std::isfinite(p->cfl))
+        return fail(c, SWE_EINVAL, "cfl must be positive and finite");
+    if (!(p->h_dry >= 0.0) || !std::isfinite(p->h_dry))
+        return fail(c, SWE_EINVAL, "h_dry must be >= 0 and finite");
+    if (!(p->dt_max > 0.0))
+        return fail(c, SWE_EINVAL, "dt_max must be positive");
+    if (p->check_every < 1)
+        return fail(c, SWE_EINVAL, "check_every must be >= 1");
+    if (!valid_block_cells(p->block_cells))
+        return fail(c, SWE_EINVAL, "block_cells must be 64, 128, 256 or 512");
+    if (p->reorder != 0 && p->reorder != 1)
+        return fail(c, SWE_EINVAL, "reorder must be 0 or 1");
+    if (p->reserved != 0) return fail(c, SWE_EINVAL, "reserved must be 0");
+    const bool g_changed = p->g != c->params.g;
+    const bool dt_changed = g_changed || p->h_dry != c->params.h_dry;
+    c->params = *p;
+    if (g_changed) c->gm2_dirty = true;
+    if (dt_changed) c->dt_valid = false;
+    return SWE_OK;
+}
+
+swe_status swe_get_params(const swe_ctx *c, swe_params *p)
+{
+    if (!c || !p) return SWE_EINVAL;
+    *p = c->params;
+    return SWE_OK;
+}
+
+swe_status swe_set_mesh(swe_ctx *c, int64_t n_nodes, const double *xy,
+                        int64_t n_cells, const int32_t *tri, int64_t n_bnd,
+                        const int32_t *bnd_nodes, const int32_t *bnd_tag)
+{
+    if (!c) return SWE_EINVAL;
+    if (!xy || !tri || n_bnd < 0 || (n_bnd > 0 && (!bnd_nodes || !bnd_tag)))
+        return fail(c, SWE_EINVAL, "null mesh array");
+    BlockMesh m;
+    std::string err;
+    if (!swe::build_block_mesh(n_nodes, xy, n_cells, tri, n_bnd, bnd_nodes,
+                               bnd_tag, c->params.block_cells,
+                               c->params.reorder != 0, SWE_MAX_TAG, m, err))
+        return fail(c, SWE_EMESH, err);
+    if (c->ws_owned && c->ws) {
+        (void)hipSetDevice(c->device);
+        (void)hipFree(c->ws);
+    }
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    c->ws_owned = false;
+    c->dev_ready = false;
+    c->mesh = std::move(m);
+    const size_t nc = size_t(c->mesh.n_cells);
+    c->z.assign(nc, 0.0);
+    c->man.assign(nc, 0.0);
+    c->h.assign(nc, 0.0);
+    c->hu.assign(nc, 0.0);
+    c->hv.assign(nc, 0.0);
+    c->z_dirty = c->man_dirty = c->state_dirty = true;
+    c->gm2_dirty = c->bc_dirty = c->clock_dirty = true;
+    c->dt_valid = false;
+    c->t_host = 0.0;
+    c->t_known = true;
+    c->step_host = 0;
+    c->last_dt_host = 0.0;
+    c->step_index = 0;
+    c->has_mesh = true;
+    return SWE_OK;
+}
+
+swe_status swe_mesh_info(const swe_ctx *c, swe_mesh_stats *o)
+{
+    if (!c || !o) return SWE_EINVAL;
+    if (!c->has_mesh) return SWE_ENOTREADY;
+    const BlockMesh &m = c->mesh;
+    o->n_nodes = m.n_nodes;
+    o->n_cells = m.n_cells;
+    o->n_edges = m.n_edges;
+    o->n_boundary_edges = m.n_bnd_edges;
+    o->n_blocks = m.n_blocks;
+    o->n_block_edges = int64_t(m.be_left.size());
+    o->block_cells = m.block_cells;
+    o->max_block_edges = m.max_block_edges;
+    o->min_inradius = m.min_inradius;
+    o->total_area = m.total_area;
+    return SWE_OK;
+}
+
+swe_status swe_get_cell_order(const swe_ctx *c, int32_t *out)
+{
+    if (!c || !out) return SWE_EINVAL;
+    if (!c->has_mesh) return SWE_ENOTREADY;
+    std::memcpy(out, c->mesh.internal_of_user.data(),
+                sizeof(int32_t) * size_t(c->mesh.n_cells));
+    return SWE_OK;
+}
+
+swe_status swe_get_geometry(const swe_ctx *c, double *area, double *inr)
+{
+    if (!c || !area || !inr) return SWE_EINVAL;
+    if (!c->has_mesh) return SWE_ENOTREADY;
+    const BlockMesh &m = c->mesh;
+    for (int64_t u = 0; u < m.n_cells; ++u) {
+        const int32_t i = m.internal_of_user[u];
+        area[u] = m.area[i];
+        inr[u] = m.inradius[i];
+    }
+    return SWE_OK;
+}
+
+swe_status swe_set_bc(swe_ctx *c, int32_t tag, swe_bc_kind kind, double value)
+{
+    if (!c) return SWE_EINVAL;
+    if (tag < 0 || tag >= SWE_MAX_TAG)
+        return fail(c, SWE_EINVAL, "tag out of range");
+    if (int(kind) < 0 || int(kind) > 4)
+        return fail(c, SWE_EINVAL, "unknown boundary kind");
+    if (!std::isfinite(value))
+        return fail(c, SWE_EINVAL, "boundary value must be finite");
+    if (kind == SWE_BC_FIXED_DEPTH && value < 0.0)
+        return fail(c, SWE_EINVAL, "fixed depth must be >= 0");
+    c->bc[tag].kind = int32_t(kind);
+    c->bc[tag].value = value;
+    c->bc_dirty = true;
+    return SWE_OK;
+}
+
+swe_status swe_set_bathymetry(swe_ctx *c, const double *z, swe_mem mem)
+{
+    if (!c) return SWE_EINVAL;
+    return set_field(c, z, mem, Field::z);
+}
+
+swe_status swe_set_manning(swe_ctx *c, const double *n, swe_mem mem)
+{
+    if (!c) return SWE_EINVAL;
+    return set_field(c, n, mem, Field::manning);
+}
+
+swe_status swe_set_state(swe_ctx *c, const double *h, const double *hu,
+                         const double *hv, swe_mem mem)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    if (!h || !hu || !hv) return fail(c, SWE_EINVAL, "null state array");
+    const int64_t nc = c->mesh.n_cells;
+    if (mem == SWE_MEM_HOST) {
+        for (int64_t u = 0; u < nc; ++u)
+            if (!(h[u] >= 0.0) || !std::isfinite(h[u]) ||
+                !std::isfinite(hu[u]) || !std::isfinite(hv[u]))
+                return fail(c, SWE_ESTATE,
+                            "state invalid at cell " + std::to_string(u) +
+                                " (need finite values and h >= 0)");
+        for (int64_t i = 0; i < nc; ++i) {
+            const int32_t u = c->mesh.user_of_internal[i];
+            c->h[i] = h[u];
+            c->hu[i] = hu[u];
+            c->hv[i] = hv[u];
+        }
+        c->state_dirty = true;
+        c->dt_valid = false;
+        return SWE_OK;
+    }
+    if (mem != SWE_MEM_DEVICE) return fail(c, SWE_EINVAL, "bad memory kind");
+    if ((st = prepare(c))) return st;
+    HIPCHK(c, swe::launch_fill_u32(c->d.flag, 0u, 1, c->stream));
+    HIPCHK(c, swe::launch_check_state(h, hu, hv, nc, c->d.flag, c->stream));
+    bool bad = false;
+    if ((st = check_flag(c, &bad))) return st;
+    if (bad)
+        return fail(c, SWE_ESTATE, "state invalid (need finite values and "
+                                   "h >= 0)");
+    const int b = c->cur_buf;
+    HIPCHK(c, swe::launch_gather3(h, hu, hv, c->d.h[b], c->d.hu[b],
+                                  c->d.hv[b], c->d.user_of_internal, nc,
+                                  c->stream));
+    c->dt_valid = false;
+    return prepare(c);
+}
+
+swe_status swe_get_state(swe_ctx *c, double *h, double *hu, double *hv,
+                         swe_mem mem)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    if (!h || !hu || !hv) return fail(c, SWE_EINVAL, "null state array");
+    if ((st = prepare(c))) return st;
+    const int64_t nc = c->mesh.n_cells;
+    const int b = c->cur_buf;
+    if (mem == SWE_MEM_DEVICE) {
+        HIPCHK(c, swe::launch_gather3(c->d.h[b], c->d.hu[b], c->d.hv[b], h,
+                                      hu, hv, c->d.internal_of_user, nc,
+                                      c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return SWE_OK;
+    }
+    if (mem != SWE_MEM_HOST) return fail(c, SWE_EINVAL, "bad memory kind");
+    std::vector<double> a(nc), bb(nc), cc(nc);
+    HIPCHK(c, hipMemcpyAsync(a.data(), c->d.h[b], nc * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(bb.data(), c->d.hu[b], nc * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(cc.data(), c->d.hv[b], nc * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int64_t u = 0; u < nc; ++u) {
+        const int32_t i = c->mesh.internal_of_user[u];
+        h[u] = a[i];
+        hu[u] = bb[i];
+        hv[u] = cc[i];
+    }
+    return SWE_OK;
+}
+
+swe_status swe_set_time(swe_ctx *c, double t, int64_t step)
+{
+    if (!c) return SWE_EINVAL;
+    if (!std::isfinite(t)) return fail(c, SWE_EINVAL, "time must be finite");
+    c->t_host = t;
+    c->t_known = true;
+    c->step_host = step;
+    c->clock_dirty = true;
+    return SWE_OK;
+}
+
+swe_status swe_get_time(swe_ctx *c, double *t, double *last_dt,
+                        int64_t *step)
+{
+    if (!c) return SWE_EINVAL;
+    if (c->dev_ready && !c->t_known) {
+        Clock ck;
+        swe_status st = read_clock(c, &ck);
+        if (st) return st;
+    }
+    if (t) *t = c->t_host;
+    if (last_dt) *last_dt = c->last_dt_host;
+    if (step) *step = c->step_host;
+    return SWE_OK;
+}
+
+swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
+                       int64_t *steps_done, double *t_now)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    if (max_steps < 0) return fail(c, SWE_EINVAL, "max_steps < 0");
+    if (std::isnan(t_end)) return fail(c, SWE_EINVAL, "t_end is NaN");
+    if ((st = prepare(c))) return st;
+    Clock ck;
+    if (!c->t_known) {
+        if ((st = read_clock(c, &ck))) return st;
+    }
+    const int64_t steps0 = c->step_host;
+    int64_t done = 0;
+    const BlockMesh &m = c->mesh;
+    swe::StepArgs a{};
+    a.blk_cell = c->d.blk_cell;
+    a.blk_edge = c->d.blk_edge;
+    a.be_left = c->d.be_left;
+    a.be_right = c->d.be_right;
+    a.be_nx = c->d.be_nx;
+    a.be_ny = c->d.be_ny;
+    a.be_len = c->d.be_len;
+    a.slots = c->d.slots;
+    a.z = c->d.z;
+    a.gm2 = c->d.gm2;
+    a.inv_area = c->d.inv_area;
+    a.area = c->d.area;
+    a.inradius = c->d.inr;
+    a.bc = c->d.bc;
+    a.clock = c->d.clock;
+    a.ledger = c->d.ledger;
+    a.g = c->params.g;
+    a.cfl = c->params.cfl;
+    a.h_dry = c->params.h_dry;
+    a.dt_max = c->params.dt_max;
+    a.t_end = t_end;
+    a.n_blocks = m.n_blocks;
+    a.emax = m.max_block_edges;
+    auto launch_n = [&](int64_t n) -> swe_status {
+        for (int64_t k = 0; k < n; ++k) {
+            const int b = c->cur_buf;
+            a.h0 = c->d.h[b];
+            a.hu0 = c->d.hu[b];
+            a.hv0 = c->d.hv[b];
+            a.h1 = c->d.h[b ^ 1];
+            a.hu1 = c->d.hu[b ^ 1];
+            a.hv1 = c->d.hv[b ^ 1];
+            a.cur = c->cur_slot;
+            a.step_index = c->step_index;
+            hipError_t e = swe::launch_step(a, m.block_cells, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
+            c->cur_buf ^= 1;
+            c->cur_slot = (c->cur_slot + 1) % 3;
+            ++c->step_index;
+        }
+        return SWE_OK;
+    };
+    if (std::isinf(t_end) && t_end > 0) {
+        if ((st = launch_n(max_steps))) return st;
+        c->t_known = false;
+        done = max_steps;
+        c->step_host = steps0 + max_steps;
+        if (t_now) {
+            if ((st = read_clock(c, &ck))) return st;
+            *t_now = c->t_host;
+        }
+        if (steps_done) *steps_done = done;
+        return SWE_OK;
+    }
+    int64_t launched = 0;
+    while (launched < max_steps && c->t_host < t_end) {
+        const int64_t n = std::min<int64_t>(c->params.check_every,
+                                            max_steps - launched);
+        if ((st = launch_n(n))) return st;
+        launched += n;
+        if ((st = read_clock(c, &ck))) return st;
+    }
+    done = c->step_host - steps0;
+    if (steps_done) *steps_done = done;
+    if (t_now) *t_now = c->t_host;
+    return SWE_OK;
+}
+
+swe_status swe_get_diagnostics(swe_ctx *c, double *mass, double *ledger,
+                               int64_t *n_wet)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    if ((st = prepare(c))) return st;
+    const int64_t nc = c->mesh.n_cells;
+    const int b = c->cur_buf;
+    HIPCHK(c, swe::launch_diag(c->d.h[b], c->d.area, nc, c->params.h_dry,
+                               c->d.part_mass, c->d.part_wet, kDiagParts,
+                               c->stream));
+    std::vector<double> pm(kDiagParts);
+    std::vector<unsigned long long> pw(kDiagParts);
+    std::vector<double> led(c->mesh.n_blocks);
+    HIPCHK(c, hipMemcpyAsync(pm.data(), c->d.part_mass, kDiagParts * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(pw.data(), c->d.part_wet, kDiagParts * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(led.data(), c->d.ledger, led.size() * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double s = 0.0, l = 0.0;
+    unsigned long long w = 0;
+    for (int k = 0; k < kDiagParts; ++k) {
+        s += pm[k];
+        w += pw[k];
+    }
+    for (double x : led) l += x;
+    if (mass) *mass = s;
+    if (ledger) *ledger = l;
+    if (n_wet) *n_wet = int64_t(w);
+    return SWE_OK;
+}
+
+swe_status swe_workspace_bytes(const swe_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return SWE_EINVAL;
+    if (!c->has_mesh) return SWE_ENOTREADY;
+    *bytes = layout(c->mesh, nullptr, nullptr);
+    return SWE_OK;
+}
+
+swe_status swe_bind_workspace(swe_ctx *c, void *ptr, size_t bytes)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    if (c->dev_ready)
+        return fail(c, SWE_ENOTREADY,
+                    "workspace must be bound before the first device use");
+    if (!ptr || (uintptr_t(ptr) & 255u))
+        return fail(c, SWE_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = layout(c->mesh, nullptr, nullptr);
+    if (bytes < need)
+        return fail(c, SWE_ENOMEM, "workspace of " + std::to_string(bytes) +
+                                       " bytes, need " + std::to_string(need));
+    c->ws = ptr;
+    c->ws_bytes = bytes;
+    c->ws_owned = false;
+    return SWE_OK;
+}
+
+}  // extern "C"

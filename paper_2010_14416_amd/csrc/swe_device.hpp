@@ -1,0 +1,96 @@
+// Device data layout and kernel launchers of the shallow-water step.
+// Shared by the HIP kernels (swe_kernels.hip) and the C interface
+// (swe_api.cpp); holds no arithmetic of the method.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace swe {
+
+// Boundary condition of one tag (sec. 3.1 and the fixed-level additions).
+struct BcEntry {
+    int32_t kind;
+    int32_t pad;
+    double value;   // Q, depth or stage (see include/swe.h)
+    double q;       // inflow discharge per unit length, Q / tag length
+};
+
+// Device-resident clock. Step n reads slot n % 3 and writes slot (n+1) % 3;
+// slot (n+2) % 3 is reset by step n for use by step n+1.
+struct Clock {
+    double t[3];                   // simulated time at the start of a step
+    unsigned long long minrs[3];   // bits of min over wet cells R_i / s_i
+    double last_dt;
+    long long steps;               // steps with dt > 0
+    unsigned int health;           // bit 0: non-finite state, bit 1: dt = inf
+    unsigned int pad;
+    long long bad_step;            // first step index that raised health
+};
+
+struct StepArgs {
+    // mesh (internal order)
+    const int32_t *blk_cell;
+    const int32_t *blk_edge;
+    const int32_t *be_left;
+    const int32_t *be_right;
+    const double *be_nx;
+    const double *be_ny;
+    const double *be_len;
+    const uint64_t *slots;
+    const double *z;
+    const double *gm2;        // g m^2 per cell
+    const double *inv_area;
+    const double *area;
+    const double *inradius;
+    const BcEntry *bc;
+    // state: U^n in, U^{n+1} out
+    const double *h0;
+    const double *hu0;
+    const double *hv0;
+    double *h1;
+    double *hu1;
+    double *hv1;
+    Clock *clock;
+    double *ledger;           // per block: mass added by the positivity fix
+    double g, cfl, h_dry, dt_max, t_end;
+    int32_t n_blocks;
+    int32_t emax;             // stride of the per-block edge results in LDS
+    int32_t cur;              // clock slot of this step
+    int32_t pad;
+    long long step_index;
+};
+
+// Bytes of dynamic LDS the step kernel needs for `block_cells` and `emax`.
+size_t step_lds_bytes(int block_cells, int emax);
+
+hipError_t launch_step(const StepArgs &a, int block_cells, hipStream_t s);
+hipError_t launch_clock_set(Clock *c, double t, long long steps,
+                            hipStream_t s);
+hipError_t launch_slot_reset(Clock *c, int slot, hipStream_t s);
+hipError_t launch_min_rs(const double *h, const double *hu, const double *hv,
+                         const double *inradius, int64_t n, double g,
+                         double h_dry, Clock *c, int cur, hipStream_t s);
+hipError_t launch_gather3(const double *a, const double *b, const double *c,
+                          double *A, double *B, double *C, const int32_t *idx,
+                          int64_t n, hipStream_t s);
+hipError_t launch_gather1(const double *a, double *A, const int32_t *idx,
+                          int64_t n, hipStream_t s);
+hipError_t launch_check_state(const double *h, const double *hu,
+                              const double *hv, int64_t n, unsigned *flag,
+                              hipStream_t s);
+hipError_t launch_check_field(const double *f, int64_t n, int nonneg,
+                              unsigned *flag, hipStream_t s);
+hipError_t launch_gm2(const double *m, double *gm2, int64_t n, double g,
+                      hipStream_t s);
+hipError_t launch_diag(const double *h, const double *area, int64_t n,
+                       double h_dry, double *part_mass,
+                       unsigned long long *part_wet, int nparts,
+                       hipStream_t s);
+hipError_t launch_fill_u32(unsigned *p, unsigned v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+
+constexpr int kDiagThreads = 256;
+
+}  // namespace swe

@@ -1,0 +1,704 @@
+// HIP kernels (gfx950) of the explicit finite-volume shallow-water step of
+// Delmas & Soulaimani (arXiv 2010.14416), sections 2-3.
+//
+// One launch of swe_step_kernel is one explicit step. A workgroup owns one
+// block of consecutive cells in the locality (Hilbert) order:
+//   1. it reads the step's time step from the device clock (eq. 15 form
+//      computed by the previous step), clipped to t_end;
+//   2. it stages its cells' depth, velocity and bed in LDS;
+//   3. it evaluates every edge of the block once (hydrostatic
+//      reconstruction eq. 28, rotation eq. 12, HLLC eqs. 17-26, bed-slope
+//      terms eq. 30, boundary fluxes sec. 3.1) and keeps both sides'
+//      contributions in LDS; neighbours in other blocks are read from HBM;
+//   4. each thread sums its cell's three contributions in local-side order,
+//      applies the semi-implicit Manning update (eqs. 31-37) and the
+//      positivity fix, writes U^{n+1} and the cell's R_i / s_i;
+//   5. the block's minimum of R_i / s_i (wave shuffles, then LDS) goes to the
+//      clock with one 64-bit atomic min on the bit pattern (positive doubles
+//      order as unsigned integers), so the next step finds its time step on
+//      the device without a host round trip.
+// State and geometry are FP64 structure-of-arrays, read once per step with
+// coalesced loads; edges on a block border are evaluated by both blocks.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <climits>
+#include <cmath>
+
+#include "swe_device.hpp"
+
+namespace swe {
+namespace {
+
+constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
+
+__device__ __forceinline__ int xcd_block(int k, int n)
+{
+    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous range of blocks so that halo cells shared by neighbouring
+    // blocks are found in the same L2.
+    const int q = n >> 3, r = n & 7;
+    const int x = k & 7, j = k >> 3;
+    return x * q + min(x, r) + j;
+}
+
+// HLLC flux in the frame of the edge normal (u normal, v tangential).
+// A side at or below h_dry is dry: depth and velocities zero. Wave speeds of
+// eqs. 19-20 with the star depth of eqs. 21-23 (rarefaction estimate clamped
+// at a vacuum), dry-bed speeds of eq. 26, contact speed of eq. 25; the
+// tangential momentum flux takes the velocity upwind of the contact.
+__device__ __forceinline__ void hllc(double g, double h_dry, double hL,
+                                     double uL, double vL, double hR,
+                                     double uR, double vR, double &G0,
+                                     double &G1, double &G2)
+{
+    const bool wetL = hL > h_dry, wetR = hR > h_dry;
+    if (!wetL) { hL = 0.0; uL = 0.0; vL = 0.0; }
+    if (!wetR) { hR = 0.0; uR = 0.0; vR = 0.0; }
+    if (!wetL && !wetR) {
+        G0 = 0.0; G1 = 0.0; G2 = 0.0;
+        return;
+    }
+    const double aL = sqrt(g * hL), aR = sqrt(g * hR);
+    double SL, SR, Ss;
+    if (!wetL) {
+        SL = uR - 2.0 * aR;
+        SR = uR + aR;
+        Ss = SL;
+    } else if (!wetR) {
+        SL = uL - aL;
+        SR = uL + 2.0 * aL;
+        Ss = SR;
+    } else {
+        const double hsum = hL + hR;
+        const double h0 = 0.5 * hsum - (uR - uL) * hsum / (4.0 * (aL + aR));
+        double hs;
+        if (h0 <= fmin(hL, hR)) {
+            const double b = fmax(0.5 * (aL + aR) + 0.25 * (uL - uR), 0.0);
+            hs = b * b / g;
+        } else {
+            const double gL = sqrt(g * (h0 + hL) / (2.0 * h0 * hL));
+            const double gR = sqrt(g * (h0 + hR) / (2.0 * h0 * hR));
+            hs = (hL * gL + hR * gR + uL - uR) / (gL + gR);
+        }
+        const double pL = hs > hL ? sqrt(hs * (hs + hL) / 2.0) / hL : 1.0;
+        const double pR = hs > hR ? sqrt(hs * (hs + hR) / 2.0) / hR : 1.0;
+        SL = uL - aL * pL;
+        SR = uR + aR * pR;
+        Ss = (SL * hR * (uR - SR) - SR * hL * (uL - SL)) /
+             (hR * (uR - SR) - hL * (uL - SL));
+    }
+    const double qL = hL * uL, qR = hR * uR;
+    if (SL >= 0.0) {
+        G0 = qL;
+        G1 = qL * uL + 0.5 * g * hL * hL;
+        G2 = qL * vL;
+    } else if (SR <= 0.0) {
+        G0 = qR;
+        G1 = qR * uR + 0.5 * g * hR * hR;
+        G2 = qR * vR;
+    } else {
+        const double FL1 = qL * uL + 0.5 * g * hL * hL;
+        const double FR1 = qR * uR + 0.5 * g * hR * hR;
+        const double inv = 1.0 / (SR - SL);
+        G0 = (SR * qL - SL * qR + SR * SL * (hR - hL)) * inv;
+        G1 = (SR * FL1 - SL * FR1 + SR * SL * (qR - qL)) * inv;
+        G2 = G0 * (Ss >= 0.0 ? vL : vR);
+    }
+}
+
+struct CellState {
+    double h, u, v, z;
+};
+
+__device__ __forceinline__ CellState load_cell(const StepArgs &a, int c)
+{
+    CellState s;
+    s.h = a.h0[c];
+    const double hu = a.hu0[c], hv = a.hv0[c];
+    s.z = a.z[c];
+    if (s.h > a.h_dry) {
+        s.u = hu / s.h;
+        s.v = hv / s.h;
+    } else {
+        s.u = 0.0;
+        s.v = 0.0;
+    }
+    return s;
+}
+
+// Contributions of one interior edge (left cell L, right cell R, unit normal
+// n from L to R, length len) to both cells' right-hand sides:
+//   cl = -len F + len (g/2)(hL**^2 - hL^2)(0, n),
+//   cr = +len F - len (g/2)(hR**^2 - hR^2)(0, n),
+// with F the back-rotated HLLC flux of the reconstructed states (eq. 28);
+// reconstructed depths at or below h_dry count as zero.
+__device__ __forceinline__ void interior_edge(double g, double h_dry,
+                                              const CellState &L,
+                                              const CellState &R, double nx,
+                                              double ny, double len,
+                                              double cl[3], double cr[3])
+{
+    const double zs = fmax(L.z, R.z);
+    double hl = L.h - (zs - L.z);
+    double hr = R.h - (zs - R.z);
+    if (hl <= h_dry) hl = 0.0;
+    if (hr <= h_dry) hr = 0.0;
+    double G0, G1, G2;
+    hllc(g, h_dry, hl, L.u * nx + L.v * ny, -L.u * ny + L.v * nx, hr,
+         R.u * nx + R.v * ny, -R.u * ny + R.v * nx, G0, G1, G2);
+    const double F1 = G1 * nx - G2 * ny;
+    const double F2 = G1 * ny + G2 * nx;
+    const double pl = 0.5 * g * (hl * hl - L.h * L.h);
+    const double pr = 0.5 * g * (hr * hr - R.h * R.h);
+    cl[0] = -len * G0;
+    cl[1] = len * (pl * nx - F1);
+    cl[2] = len * (pl * ny - F2);
+    cr[0] = len * G0;
+    cr[1] = len * (F1 - pr * nx);
+    cr[2] = len * (F2 - pr * ny);
+}
+
+// Contribution of a boundary edge of cell L (outward normal n): wall,
+// transmissive, inflow of discharge q per unit length, or a ghost state of
+// fixed depth / fixed surface elevation with the cell's velocity.
+__device__ __forceinline__ void boundary_edge(double g, double h_dry,
+                                              const BcEntry &bc,
+                                              const CellState &L, double nx,
+                                              double ny, double len,
+                                              double cl[3])
+{
+    const double un = L.u * nx + L.v * ny, ut = -L.u * ny + L.v * nx;
+    double G0, G1, G2;
+    switch (bc.kind) {
+    case 1:   // transmissive
+        G0 = L.h * un;
+        G1 = G0 * un + 0.5 * g * L.h * L.h;
+        G2 = G0 * ut;
+        break;
+    case 2:   // inflow
+        G0 = -bc.q;
+        G1 = (L.h > h_dry ? bc.q * bc.q / L.h : 0.0) + 0.5 * g * L.h * L.h;
+        G2 = 0.0;
+        break;
+    case 3:   // fixed depth
+        hllc(g, h_dry, L.h, un, ut, bc.value, un, ut, G0, G1, G2);
+        break;
+    case 4:   // fixed water-surface elevation
+        hllc(g, h_dry, L.h, un, ut, fmax(bc.value - L.z, 0.0), un, ut, G0,
+             G1, G2);
+        break;
+    default:  // wall
+        G0 = 0.0;
+        G1 = 0.5 * g * L.h * L.h;
+        G2 = 0.0;
+        break;
+    }
+    cl[0] = -len * G0;
+    cl[1] = -len * (G1 * nx - G2 * ny);
+    cl[2] = -len * (G1 * ny + G2 * nx);
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
+{
+    extern __shared__ double lds[];
+    __shared__ double red_min[NT / 64];
+    __shared__ double red_sum[NT / 64];
+    __shared__ unsigned red_bad[NT / 64];
+    double *s_h = lds;
+    double *s_u = s_h + NT;
+    double *s_v = s_u + NT;
+    double *s_z = s_v + NT;
+    double *s_c = s_z + NT;   // 6 x emax: left contributions, then right
+    const int emax = a.emax;
+
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int c0 = a.blk_cell[blk];
+    const int nc = a.blk_cell[blk + 1] - c0;
+    const int e0 = a.blk_edge[blk];
+    const int ne = a.blk_edge[blk + 1] - e0;
+    const int tid = threadIdx.x;
+    const double g = a.g, h_dry = a.h_dry;
+
+    // time step of this step: CFL * min R/s of U^n, bounded, clipped to t_end
+    const int cur = a.cur;
+    const int nxt = cur == 2 ? 0 : cur + 1;
+    const double mrs = __longlong_as_double((long long)a.clock->minrs[cur]);
+    const double t = a.clock->t[cur];
+    double dt = fmin(a.cfl * mrs, a.dt_max);
+    const double rem = a.t_end - t;
+    double tn;
+    if (dt >= rem) {
+        dt = rem > 0.0 ? rem : 0.0;
+        tn = rem > 0.0 ? a.t_end : t;
+    } else {
+        tn = t + dt;
+    }
+    const bool unbounded = !(dt < INFINITY);
+    if (unbounded) {
+        dt = 0.0;
+        tn = t;
+    }
+
+    // stage this block's cells
+    const bool own = tid < nc;
+    const int i = c0 + tid;
+    double h = 0.0, hu = 0.0, hv = 0.0;
+    if (own) {
+        h = a.h0[i];
+        hu = a.hu0[i];
+        hv = a.hv0[i];
+        s_h[tid] = h;
+        s_z[tid] = a.z[i];
+        if (h > h_dry) {
+            s_u[tid] = hu / h;
+            s_v[tid] = hv / h;
+        } else {
+            s_u[tid] = 0.0;
+            s_v[tid] = 0.0;
+        }
+    }
+    __syncthreads();
+
+    // every edge of the block once
+    for (int k = tid; k < ne; k += NT) {
+        const int l = a.be_left[e0 + k];
+        const int r = a.be_right[e0 + k];
+        const double nx = a.be_nx[e0 + k];
+        const double ny = a.be_ny[e0 + k];
+        const double len = a.be_len[e0 + k];
+        CellState L;
+        const unsigned ll = unsigned(l - c0);
+        if (ll < unsigned(nc)) {
+            L.h = s_h[ll]; L.u = s_u[ll]; L.v = s_v[ll]; L.z = s_z[ll];
+        } else {
+            L = load_cell(a, l);
+        }
+        double cl[3], cr[3];
+        if (r >= 0) {
+            CellState R;
+            const unsigned rr = unsigned(r - c0);
+            if (rr < unsigned(nc)) {
+                R.h = s_h[rr]; R.u = s_u[rr]; R.v = s_v[rr]; R.z = s_z[rr];
+            } else {
+                R = load_cell(a, r);
+            }
+            interior_edge(g, h_dry, L, R, nx, ny, len, cl, cr);
+        } else {
+            const BcEntry bc = a.bc[-1 - r];
+            boundary_edge(g, h_dry, bc, L, nx, ny, len, cl);
+            cr[0] = 0.0; cr[1] = 0.0; cr[2] = 0.0;
+        }
+        s_c[k] = cl[0];
+        s_c[emax + k] = cl[1];
+        s_c[2 * emax + k] = cl[2];
+        s_c[3 * emax + k] = cr[0];
+        s_c[4 * emax + k] = cr[1];
+        s_c[5 * emax + k] = cr[2];
+    }
+    __syncthreads();
+
+    // cell update
+    double rs = INFINITY, clamp = 0.0;
+    unsigned bad = 0;
+    if (own) {
+        const unsigned long long pk = a.slots[i];
+        double R0 = 0.0, R1 = 0.0, R2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const unsigned s = unsigned(pk >> (16 * k)) & 0xffffu;
+            const double *src = s_c + (s >> 15) * 3 * emax + (s & 0x7fffu);
+            R0 += src[0];
+            R1 += src[emax];
+            R2 += src[2 * emax];
+        }
+        double hn = h, hun = hu, hvn = hv;
+        if (dt > 0.0) {
+            const double ia = a.inv_area[i];
+            const double bh = R0 * ia, bx = R1 * ia, by = R2 * ia;
+            const double dh = dt * bh;
+            const double qn = sqrt(hu * hu + hv * hv);
+            double dqx, dqy;
+            if (h > h_dry && qn > 0.0) {
+                // semi-implicit Manning: S_f = -c|q|q, c = g m^2 h^(-7/3);
+                // (I - dt/2 dS/dq) dq = dt (R_q/A + S_f) + dt/2 (dS/dh) dh
+                const double c = a.gm2[i] / (h * h * cbrt(h));
+                const double cq = c * qn;
+                const double iq = 1.0 / qn;
+                const double jh = (7.0 / 3.0) * cq / h;
+                const double m11 = 1.0 + 0.5 * dt * c * (qn + hu * hu * iq);
+                const double m12 = 0.5 * dt * c * hu * hv * iq;
+                const double m22 = 1.0 + 0.5 * dt * c * (qn + hv * hv * iq);
+                const double rx = dt * (bx - cq * hu) + 0.5 * dt * jh * hu * dh;
+                const double ry = dt * (by - cq * hv) + 0.5 * dt * jh * hv * dh;
+                const double idet = 1.0 / (m11 * m22 - m12 * m12);
+                dqx = (rx * m22 - m12 * ry) * idet;
+                dqy = (m11 * ry - m12 * rx) * idet;
+            } else {
+                dqx = dt * bx;
+                dqy = dt * by;
+            }
+            hn = h + dh;
+            hun = hu + dqx;
+            hvn = hv + dqy;
+            if (hn < 0.0) {
+                clamp = -hn * a.area[i];
+                hn = 0.0;
+            }
+            if (hn <= h_dry) {
+                hun = 0.0;
+                hvn = 0.0;
+            }
+        }
+        a.h1[i] = hn;
+        a.hu1[i] = hun;
+        a.hv1[i] = hvn;
+        if (!isfinite(hn) || !isfinite(hun) || !isfinite(hvn)) bad = 1u;
+        if (hn > h_dry) {
+            const double u = hun / hn, v = hvn / hn;
+            rs = a.inradius[i] / (sqrt(g * hn) + sqrt(u * u + v * v));
+        }
+    }
+
+    // block reductions: min R/s, sum of clamped mass, any non-finite value
+    rs = wave_min(rs);
+    clamp = wave_sum(clamp);
+    const unsigned long long ballot = __ballot(bad != 0u);
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane == 0) {
+        red_min[wave] = rs;
+        red_sum[wave] = clamp;
+        red_bad[wave] = ballot != 0ull ? 1u : 0u;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double m = red_min[0], cs = red_sum[0];
+        unsigned anybad = red_bad[0];
+        for (int w = 1; w < NT / 64; ++w) {
+            m = fmin(m, red_min[w]);
+            cs += red_sum[w];
+            anybad |= red_bad[w];
+        }
+        if (m < INFINITY)
+            atomicMin(&a.clock->minrs[nxt],
+                      (unsigned long long)__double_as_longlong(m));
+        if (cs != 0.0) a.ledger[blk] += cs;
+        if (anybad || unbounded) {
+            atomicOr(&a.clock->health, (anybad ? 1u : 0u) | (unbounded ? 2u : 0u));
+            atomicMin(&a.clock->bad_step, a.step_index);
+        }
+        if (blk == 0) {
+            const int nn = nxt == 2 ? 0 : nxt + 1;
+            a.clock->t[nxt] = tn;
+            a.clock->last_dt = dt;
+            if (dt > 0.0) a.clock->steps += 1;
+            atomicExch(&a.clock->minrs[nn], kInfBits);
+        }
+    }
+}
+
+__global__ void clock_set_kernel(Clock *c, double t, long long steps)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->t[0] = t;
+        c->t[1] = t;
+        c->t[2] = t;
+        c->minrs[0] = kInfBits;
+        c->minrs[1] = kInfBits;
+        c->minrs[2] = kInfBits;
+        c->last_dt = 0.0;
+        c->steps = steps;
+        c->health = 0u;
+        c->pad = 0u;
+        c->bad_step = LLONG_MAX;
+    }
+}
+
+__global__ void slot_reset_kernel(Clock *c, int slot)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomicExch(&c->minrs[slot], kInfBits);
+}
+
+__global__ __launch_bounds__(256) void min_rs_kernel(
+    const double *__restrict__ h, const double *__restrict__ hu,
+    const double *__restrict__ hv, const double *__restrict__ inr, int64_t n,
+    double g, double h_dry, Clock *c, int cur)
+{
+    __shared__ double red[4];
+    double rs = INFINITY;
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n;
+         k += int64_t(gridDim.x) * blockDim.x) {
+        const double hk = h[k];
+        if (hk > h_dry) {
+            const double u = hu[k] / hk, v = hv[k] / hk;
+            rs = fmin(rs, inr[k] / (sqrt(g * hk) + sqrt(u * u + v * v)));
+        }
+    }
+    rs = wave_min(rs);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rs;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+        if (m < INFINITY)
+            atomicMin(&c->minrs[cur], (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+__global__ __launch_bounds__(256) void gather3_kernel(
+    const double *__restrict__ a, const double *__restrict__ b,
+    const double *__restrict__ c, double *__restrict__ A,
+    double *__restrict__ B, double *__restrict__ C,
+    const int32_t *__restrict__ idx, int64_t n)
+{
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n;
+         k += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t j = idx[k];
+        A[k] = a[j];
+        B[k] = b[j];
+        C[k] = c[j];
+    }
+}
+
+__global__ __launch_bounds__(256) void gather1_kernel(
+    const double *__restrict__ a, double *__restrict__ A,
+    const int32_t *__restrict__ idx, int64_t n)
+{
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n;
+         k += int64_t(gridDim.x) * blockDim.x)
+        A[k] = a[idx[k]];
+}
+
+__global__ __launch_bounds__(256) void check_state_kernel(
+    const double *__restrict__ h, const double *__restrict__ hu,
+    const double *__restrict__ hv, int64_t n, unsigned *flag)
+{
+    bool bad = false;
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n;
+         k += int64_t(gridDim.x) * blockDim.x) {
+        const double hk = h[k];
+        if (!(hk >= 0.0) || !isfinite(hk) || !isfinite(hu[k]) ||
+            !isfinite(hv[k]))
+            bad = true;
+    }
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+__global__ __launch_bounds__(256) void check_field_kernel(
+    const double *__restrict__ f, int64_t n, int nonneg, unsigned *flag)
+{
+    bool bad = false;
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n;
+         k += int64_t(gridDim.x) * blockDim.x) {
+        const double v = f[k];
+        if (!isfinite(v) || (nonneg && !(v >= 0.0))) bad = true;
+    }
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+__global__ __launch_bounds__(256) void gm2_kernel(
+    const double *__restrict__ m, double *__restrict__ gm2, int64_t n,
+    double g)
+{
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n;
+         k += int64_t(gridDim.x) * blockDim.x)
+        gm2[k] = g * m[k] * m[k];
+}
+
+// Per-part partial sums of |Omega_i| h_i and of wet cells; part p covers a
+// fixed contiguous range, summed in a fixed order, so the result does not
+// depend on scheduling.
+__global__ __launch_bounds__(kDiagThreads) void diag_kernel(
+    const double *__restrict__ h, const double *__restrict__ area, int64_t n,
+    double h_dry, double *part_mass, unsigned long long *part_wet)
+{
+    __shared__ double sm[kDiagThreads / 64];
+    __shared__ unsigned long long sw[kDiagThreads / 64];
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t k0 = int64_t(blockIdx.x) * per;
+    const int64_t k1 = min(n, k0 + per);
+    double m = 0.0;
+    unsigned long long w = 0;
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+        m += area[k] * h[k];
+        w += h[k] > h_dry ? 1ull : 0ull;
+    }
+    m = wave_sum(m);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+    if ((threadIdx.x & 63) == 0) {
+        sm[threadIdx.x >> 6] = m;
+        sw[threadIdx.x >> 6] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        unsigned long long c = 0;
+        for (int q = 0; q < kDiagThreads / 64; ++q) {
+            s += sm[q];
+            c += sw[q];
+        }
+        part_mass[blockIdx.x] = s;
+        part_wet[blockIdx.x] = c;
+    }
+}
+
+__global__ __launch_bounds__(256) void fill_u32_kernel(unsigned *p,
+                                                       unsigned v, int64_t n)
+{
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n;
+         k += int64_t(gridDim.x) * blockDim.x)
+        p[k] = v;
+}
+
+__global__ __launch_bounds__(256) void fill_f64_kernel(double *p, double v,
+                                                       int64_t n)
+{
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n;
+         k += int64_t(gridDim.x) * blockDim.x)
+        p[k] = v;
+}
+
+inline unsigned grid_for(int64_t n, int threads = 256)
+{
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    return unsigned(b);
+}
+
+}  // namespace
+
+size_t step_lds_bytes(int block_cells, int emax)
+{
+    return sizeof(double) * (4 * size_t(block_cells) + 6 * size_t(emax));
+}
+
+hipError_t launch_step(const StepArgs &a, int block_cells, hipStream_t s)
+{
+    const size_t lds = step_lds_bytes(block_cells, a.emax);
+    switch (block_cells) {
+    case 64:
+        hipLaunchKernelGGL(swe_step_kernel<64>, dim3(a.n_blocks), dim3(64),
+                           lds, s, a);
+        break;
+    case 128:
+        hipLaunchKernelGGL(swe_step_kernel<128>, dim3(a.n_blocks), dim3(128),
+                           lds, s, a);
+        break;
+    case 256:
+        hipLaunchKernelGGL(swe_step_kernel<256>, dim3(a.n_blocks), dim3(256),
+                           lds, s, a);
+        break;
+    case 512:
+        hipLaunchKernelGGL(swe_step_kernel<512>, dim3(a.n_blocks), dim3(512),
+                           lds, s, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_clock_set(Clock *c, double t, long long steps,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(clock_set_kernel, dim3(1), dim3(64), 0, s, c, t, steps);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_reset(Clock *c, int slot, hipStream_t s)
+{
+    hipLaunchKernelGGL(slot_reset_kernel, dim3(1), dim3(64), 0, s, c, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_min_rs(const double *h, const double *hu, const double *hv,
+                         const double *inr, int64_t n, double g, double h_dry,
+                         Clock *c, int cur, hipStream_t s)
+{
+    hipLaunchKernelGGL(min_rs_kernel, dim3(grid_for(n)), dim3(256), 0, s, h,
+                       hu, hv, inr, n, g, h_dry, c, cur);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather3(const double *a, const double *b, const double *c,
+                          double *A, double *B, double *C, const int32_t *idx,
+                          int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(gather3_kernel, dim3(grid_for(n)), dim3(256), 0, s, a,
+                       b, c, A, B, C, idx, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather1(const double *a, double *A, const int32_t *idx,
+                          int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(gather1_kernel, dim3(grid_for(n)), dim3(256), 0, s, a,
+                       A, idx, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_state(const double *h, const double *hu,
+                              const double *hv, int64_t n, unsigned *flag,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(check_state_kernel, dim3(grid_for(n)), dim3(256), 0, s,
+                       h, hu, hv, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_field(const double *f, int64_t n, int nonneg,
+                              unsigned *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(check_field_kernel, dim3(grid_for(n)), dim3(256), 0, s,
+                       f, n, nonneg, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_gm2(const double *m, double *gm2, int64_t n, double g,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(gm2_kernel, dim3(grid_for(n)), dim3(256), 0, s, m, gm2,
+                       n, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const double *h, const double *area, int64_t n,
+                       double h_dry, double *part_mass,
+                       unsigned long long *part_wet, int nparts, hipStream_t s)
+{
+    hipLaunchKernelGGL(diag_kernel, dim3(nparts), dim3(kDiagThreads), 0, s, h,
+                       area, n, h_dry, part_mass, part_wet);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned *p, unsigned v, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n)), dim3(256), 0, s, p,
+                       v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(n)), dim3(256), 0, s, p,
+                       v, n);
+    return hipGetLastError();
+}
+
+}  // namespace swe

@@ -1,0 +1,50 @@
+// Host-side mesh preparation for the shallow-water step: validation,
+// counter-clockwise orientation, unique edges with their unit normals,
+// cell geometry (area, inscribed radius), a space-filling-curve cell order,
+// and the per-block edge lists the fused step kernel consumes.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace swe {
+
+// Device-facing mesh in the internal (locality) cell order.
+struct BlockMesh {
+    int64_t n_nodes = 0, n_cells = 0, n_edges = 0, n_bnd_edges = 0;
+    int32_t block_cells = 256;
+    int32_t n_blocks = 0;
+    int32_t max_block_edges = 0;
+    double min_inradius = 0.0, total_area = 0.0;
+
+    // cell order: internal_of_user[u] = i, user_of_internal[i] = u
+    std::vector<int32_t> internal_of_user, user_of_internal;
+
+    // per internal cell
+    std::vector<double> area, inv_area, inradius;
+    std::vector<uint64_t> slots;   // 3 x 16 bits: block-edge slot | side<<15
+
+    // per block: [blk_cell[b], blk_cell[b+1]) cells,
+    //            [blk_edge[b], blk_edge[b+1]) block-edge records
+    std::vector<int32_t> blk_cell, blk_edge;
+
+    // per block-edge record
+    //   left  : internal index of the cell on the left of the edge
+    //   right : internal index of the right cell, or -1 - tag on the boundary
+    //   n     : unit normal from left to right (outward on the boundary)
+    std::vector<int32_t> be_left, be_right;
+    std::vector<double> be_nx, be_ny, be_len;
+
+    // total boundary length per tag (inflow discharge per unit length)
+    std::vector<double> tag_length;
+};
+
+// Builds the block mesh. Returns false and sets err on an invalid mesh.
+bool build_block_mesh(int64_t n_nodes, const double *xy, int64_t n_cells,
+                      const int32_t *tri, int64_t n_bnd,
+                      const int32_t *bnd_nodes, const int32_t *bnd_tag,
+                      int32_t block_cells, bool reorder, int32_t max_tag,
+                      BlockMesh &out, std::string &err);
+
+}  // namespace swe

@@ -1,0 +1,413 @@
+"""Thin ctypes binding of libswe.so (include/swe.h), same function names.
+
+Only argument marshalling happens here: numpy arrays are passed as host
+memory, torch CUDA tensors (float64, contiguous) as device memory. Every step
+of the method runs in the library's HIP kernels. The library must have been
+built (``python -m paper_2010_14416_amd.build``); loading fails loudly
+otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswe.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "swe.h")
+
+SWE_OK = 0
+SWE_EINVAL = -1
+SWE_EMESH = -2
+SWE_ESTATE = -3
+SWE_EDEVICE = -4
+SWE_ENOMEM = -5
+SWE_ENOTREADY = -6
+SWE_ENUMERIC = -7
+STATUS_NAMES = {0: "SWE_OK", -1: "SWE_EINVAL", -2: "SWE_EMESH",
+                -3: "SWE_ESTATE", -4: "SWE_EDEVICE", -5: "SWE_ENOMEM",
+                -6: "SWE_ENOTREADY", -7: "SWE_ENUMERIC"}
+
+SWE_BC_WALL = 0
+SWE_BC_TRANSMISSIVE = 1
+SWE_BC_INFLOW = 2
+SWE_BC_FIXED_DEPTH = 3
+SWE_BC_FIXED_STAGE = 4
+SWE_MEM_HOST = 0
+SWE_MEM_DEVICE = 1
+SWE_MAX_TAG = 1024
+
+
+class swe_params(C.Structure):
+    _fields_ = [("g", C.c_double), ("cfl", C.c_double), ("h_dry", C.c_double),
+                ("dt_max", C.c_double), ("check_every", C.c_int32),
+                ("block_cells", C.c_int32), ("reorder", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class swe_mesh_stats(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_cells", C.c_int64),
+                ("n_edges", C.c_int64), ("n_boundary_edges", C.c_int64),
+                ("n_blocks", C.c_int64), ("n_block_edges", C.c_int64),
+                ("block_cells", C.c_int32), ("max_block_edges", C.c_int32),
+                ("min_inradius", C.c_double), ("total_area", C.c_double)]
+
+
+class SweError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+_p = C.c_void_p
+_pd = C.POINTER(C.c_double)
+_pi32 = C.POINTER(C.c_int32)
+_pi64 = C.POINTER(C.c_int64)
+
+
+def load():
+    """Loads libswe.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python -m paper_2010_14416_amd.build` (the GPU path has no "
+            "fallback)")
+    L = C.CDLL(LIB_PATH)
+    st = C.c_int
+    L.swe_abi_version.restype = C.c_int
+    L.swe_default_params.restype = st
+    L.swe_default_params.argtypes = [C.POINTER(swe_params)]
+    L.swe_create.restype = st
+    L.swe_create.argtypes = [C.POINTER(_p), C.c_int]
+    L.swe_destroy.argtypes = [_p]
+    L.swe_last_error.restype = C.c_char_p
+    L.swe_last_error.argtypes = [_p]
+    L.swe_set_stream.restype = st
+    L.swe_set_stream.argtypes = [_p, _p]
+    L.swe_set_params.restype = st
+    L.swe_set_params.argtypes = [_p, C.POINTER(swe_params)]
+    L.swe_get_params.restype = st
+    L.swe_get_params.argtypes = [_p, C.POINTER(swe_params)]
+    L.swe_set_mesh.restype = st
+    L.swe_set_mesh.argtypes = [_p, C.c_int64, _pd, C.c_int64, _pi32,
+                               C.c_int64, _pi32, _pi32]
+    L.swe_mesh_info.restype = st
+    L.swe_mesh_info.argtypes = [_p, C.POINTER(swe_mesh_stats)]
+    L.swe_get_cell_order.restype = st
+    L.swe_get_cell_order.argtypes = [_p, _pi32]
+    L.swe_get_geometry.restype = st
+    L.swe_get_geometry.argtypes = [_p, _pd, _pd]
+    L.swe_set_bc.restype = st
+    L.swe_set_bc.argtypes = [_p, C.c_int32, C.c_int, C.c_double]
+    for name in ("swe_set_bathymetry", "swe_set_manning"):
+        f = getattr(L, name)
+        f.restype = st
+        f.argtypes = [_p, _p, C.c_int]
+    L.swe_set_state.restype = st
+    L.swe_set_state.argtypes = [_p, _p, _p, _p, C.c_int]
+    L.swe_get_state.restype = st
+    L.swe_get_state.argtypes = [_p, _p, _p, _p, C.c_int]
+    L.swe_set_time.restype = st
+    L.swe_set_time.argtypes = [_p, C.c_double, C.c_int64]
+    L.swe_get_time.restype = st
+    L.swe_get_time.argtypes = [_p, _pd, _pd, _pi64]
+    L.swe_advance.restype = st
+    L.swe_advance.argtypes = [_p, C.c_int64, C.c_double, _pi64, _pd]
+    L.swe_get_diagnostics.restype = st
+    L.swe_get_diagnostics.argtypes = [_p, _pd, _pd, _pi64]
+    L.swe_workspace_bytes.restype = st
+    L.swe_workspace_bytes.argtypes = [_p, C.POINTER(C.c_size_t)]
+    L.swe_bind_workspace.restype = st
+    L.swe_bind_workspace.argtypes = [_p, _p, C.c_size_t]
+    _lib = L
+    return L
+
+
+def header_functions():
+    """Names of the functions include/swe.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(swe_[a-z_]+)\s*\(", text)))
+
+
+def _check(ctx, status):
+    if status != SWE_OK:
+        msg = load().swe_last_error(ctx)
+        raise SweError(status, msg.decode() if msg else "")
+
+
+# -------------------------------------------------------------- marshalling
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _cell_ptr(x, n, name):
+    """(pointer, mem kind, keep-alive) of a per-cell float64 array."""
+    if _is_torch(x):
+        import torch
+        if x.dtype != torch.float64 or x.numel() != n or \
+                not x.is_contiguous():
+            raise ValueError(f"{name}: need a contiguous float64 tensor of "
+                             f"{n} elements")
+        if x.is_cuda:
+            return C.c_void_p(x.data_ptr()), SWE_MEM_DEVICE, x
+        x = x.numpy()
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    if a.size != n:
+        raise ValueError(f"{name}: need {n} values, got {a.size}")
+    return C.c_void_p(a.ctypes.data), SWE_MEM_HOST, a
+
+
+# -------------------------------------------------------- the C functions
+
+def swe_abi_version():
+    return load().swe_abi_version()
+
+
+def swe_default_params():
+    p = swe_params()
+    _check(None, load().swe_default_params(C.byref(p)))
+    return p
+
+
+def swe_create(device=0):
+    ctx = C.c_void_p()
+    _check(None, load().swe_create(C.byref(ctx), int(device)))
+    return ctx
+
+
+def swe_destroy(ctx):
+    load().swe_destroy(ctx)
+
+
+def swe_last_error(ctx):
+    m = load().swe_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def swe_set_stream(ctx, stream):
+    """stream: an int/pointer (hipStream_t) or a torch.cuda.Stream."""
+    if hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    _check(ctx, load().swe_set_stream(ctx, C.c_void_p(stream or 0)))
+
+
+def swe_set_params(ctx, params):
+    _check(ctx, load().swe_set_params(ctx, C.byref(params)))
+
+
+def swe_get_params(ctx):
+    p = swe_params()
+    _check(ctx, load().swe_get_params(ctx, C.byref(p)))
+    return p
+
+
+def swe_set_mesh(ctx, xy, tri, bnd=None, bnd_tag=None):
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+    if bnd is None:
+        bnd = np.zeros((0, 2), np.int32)
+        bnd_tag = np.zeros(0, np.int32)
+    bnd = np.ascontiguousarray(bnd, dtype=np.int32).reshape(-1, 2)
+    bnd_tag = np.ascontiguousarray(bnd_tag, dtype=np.int32).reshape(-1)
+    if bnd_tag.size != bnd.shape[0]:
+        raise ValueError("bnd_tag must have one tag per boundary segment")
+    _check(ctx, load().swe_set_mesh(
+        ctx, xy.shape[0], xy.ctypes.data_as(_pd), tri.shape[0],
+        tri.ctypes.data_as(_pi32), bnd.shape[0], bnd.ctypes.data_as(_pi32),
+        bnd_tag.ctypes.data_as(_pi32)))
+
+
+def swe_mesh_info(ctx):
+    s = swe_mesh_stats()
+    _check(ctx, load().swe_mesh_info(ctx, C.byref(s)))
+    return {k: getattr(s, k) for k, _ in swe_mesh_stats._fields_}
+
+
+def swe_get_cell_order(ctx):
+    n = swe_mesh_info(ctx)["n_cells"]
+    out = np.empty(n, np.int32)
+    _check(ctx, load().swe_get_cell_order(ctx, out.ctypes.data_as(_pi32)))
+    return out
+
+
+def swe_get_geometry(ctx):
+    n = swe_mesh_info(ctx)["n_cells"]
+    area, inr = np.empty(n), np.empty(n)
+    _check(ctx, load().swe_get_geometry(ctx, area.ctypes.data_as(_pd),
+                                        inr.ctypes.data_as(_pd)))
+    return area, inr
+
+
+def swe_set_bc(ctx, tag, kind, value=0.0):
+    _check(ctx, load().swe_set_bc(ctx, int(tag), int(kind), float(value)))
+
+
+def _n_cells(ctx):
+    return swe_mesh_info(ctx)["n_cells"]
+
+
+def swe_set_bathymetry(ctx, z):
+    p, mem, keep = _cell_ptr(z, _n_cells(ctx), "z")
+    _check(ctx, load().swe_set_bathymetry(ctx, p, mem))
+    del keep
+
+
+def swe_set_manning(ctx, n):
+    p, mem, keep = _cell_ptr(n, _n_cells(ctx), "manning")
+    _check(ctx, load().swe_set_manning(ctx, p, mem))
+    del keep
+
+
+def swe_set_state(ctx, h, hu, hv):
+    nc = _n_cells(ctx)
+    ph, mh, k1 = _cell_ptr(h, nc, "h")
+    pu, mu, k2 = _cell_ptr(hu, nc, "hu")
+    pv, mv, k3 = _cell_ptr(hv, nc, "hv")
+    if not (mh == mu == mv):
+        raise ValueError("h, hu, hv must all be host or all device arrays")
+    _check(ctx, load().swe_set_state(ctx, ph, pu, pv, mh))
+    del k1, k2, k3
+
+
+def swe_get_state(ctx, out=None):
+    """Returns (h, hu, hv) as numpy arrays, or fills `out` (three float64
+    CUDA tensors or numpy arrays) and returns it."""
+    nc = _n_cells(ctx)
+    if out is None:
+        out = (np.empty(nc), np.empty(nc), np.empty(nc))
+    ptrs = [_cell_ptr(a, nc, "out") for a in out]
+    mems = {m for _, m, _ in ptrs}
+    if len(mems) != 1:
+        raise ValueError("outputs must all be host or all device arrays")
+    if mems == {SWE_MEM_HOST} and any(
+            not isinstance(a, np.ndarray) for a in out):
+        raise ValueError("host outputs must be numpy arrays")
+    _check(ctx, load().swe_get_state(ctx, ptrs[0][0], ptrs[1][0], ptrs[2][0],
+                                     mems.pop()))
+    return out
+
+
+def swe_set_time(ctx, t, step=0):
+    _check(ctx, load().swe_set_time(ctx, float(t), int(step)))
+
+
+def swe_get_time(ctx):
+    t, dt, step = C.c_double(), C.c_double(), C.c_int64()
+    _check(ctx, load().swe_get_time(ctx, C.byref(t), C.byref(dt),
+                                    C.byref(step)))
+    return t.value, dt.value, step.value
+
+
+def swe_advance(ctx, max_steps, t_end=math.inf, want_time=False):
+    """Returns (steps_done, t_now); t_now is None unless want_time or t_end
+    is finite (reading it synchronises)."""
+    done = C.c_int64()
+    t = C.c_double()
+    sync = want_time or math.isfinite(t_end)
+    _check(ctx, load().swe_advance(ctx, int(max_steps), float(t_end),
+                                   C.byref(done),
+                                   C.byref(t) if sync else None))
+    return done.value, (t.value if sync else None)
+
+
+def swe_get_diagnostics(ctx):
+    m, led, nw = C.c_double(), C.c_double(), C.c_int64()
+    _check(ctx, load().swe_get_diagnostics(ctx, C.byref(m), C.byref(led),
+                                           C.byref(nw)))
+    return m.value, led.value, nw.value
+
+
+def swe_workspace_bytes(ctx):
+    b = C.c_size_t()
+    _check(ctx, load().swe_workspace_bytes(ctx, C.byref(b)))
+    return b.value
+
+
+def swe_bind_workspace(ctx, ptr, nbytes):
+    _check(ctx, load().swe_bind_workspace(ctx, C.c_void_p(ptr), int(nbytes)))
+
+
+# ------------------------------------------------------------ convenience
+
+class Solver:
+    """One context set up from a workloads.Case. With workspace="torch" the
+    device memory is a torch uint8 tensor bound through swe_bind_workspace;
+    with stream="torch" kernels run on torch's current stream."""
+
+    def __init__(self, case, device=0, workspace="torch", stream="torch",
+                 block_cells=256, reorder=True, params=None):
+        self.ctx = swe_create(device)
+        self._ws = None
+        self.device = device
+        try:
+            p = swe_default_params()
+            p.g, p.cfl, p.h_dry = case.g, case.cfl, case.h_dry
+            p.block_cells = int(block_cells)
+            p.reorder = 1 if reorder else 0
+            if params:
+                for k, v in params.items():
+                    setattr(p, k, v)
+            swe_set_params(self.ctx, p)
+            swe_set_mesh(self.ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
+            for tag, (kind, value) in case.bc.items():
+                swe_set_bc(self.ctx, tag, kind, value)
+            swe_set_bathymetry(self.ctx, case.z)
+            swe_set_manning(self.ctx, case.manning)
+            swe_set_state(self.ctx, case.h, case.hu, case.hv)
+            if stream == "torch" or workspace == "torch":
+                import torch
+                dev = torch.device("cuda", device)
+                if stream == "torch":
+                    self.stream = torch.cuda.current_stream(dev)
+                    swe_set_stream(self.ctx, self.stream.cuda_stream)
+                if workspace == "torch":
+                    nb = swe_workspace_bytes(self.ctx)
+                    self._ws = torch.empty(nb + 256, dtype=torch.uint8,
+                                           device=dev)
+                    base = self._ws.data_ptr()
+                    off = (-base) % 256
+                    swe_bind_workspace(self.ctx, base + off, nb)
+            elif stream is not None:
+                swe_set_stream(self.ctx, stream)
+        except Exception:
+            self.close()
+            raise
+
+    def info(self):
+        return swe_mesh_info(self.ctx)
+
+    def advance(self, steps, t_end=math.inf, want_time=False):
+        return swe_advance(self.ctx, steps, t_end, want_time)
+
+    def state(self, out=None):
+        return swe_get_state(self.ctx, out)
+
+    def set_state(self, h, hu, hv):
+        swe_set_state(self.ctx, h, hu, hv)
+
+    def time(self):
+        return swe_get_time(self.ctx)
+
+    def diagnostics(self):
+        return swe_get_diagnostics(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            swe_destroy(self.ctx)
+            self.ctx = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,186 @@
+"""CPU tests of the C interface: the library loads and exports every symbol
+of include/swe.h, and its host-side logic (mesh validation, edges, geometry,
+cell order, blocks, input validation) behaves as documented. No GPU call is
+made: the library touches the device only on first device use."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from paper_2010_14416_amd import swe as S
+
+
+@pytest.fixture
+def ctx():
+    c = S.swe_create(0)
+    yield c
+    S.swe_destroy(c)
+
+
+def test_library_exports_every_declared_symbol():
+    L = S.load()
+    names = S.header_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing
+    assert S.swe_abi_version() == 1
+
+
+def test_default_params():
+    p = S.swe_default_params()
+    assert (p.g, p.cfl, p.h_dry) == (9.81, 0.9, 1e-6)
+    assert math.isinf(p.dt_max) and p.block_cells == 256 and p.reorder == 1
+
+
+@pytest.mark.parametrize("case", [
+    W.dam_break_canal(),
+    W.bumps_canal(nx=37, ny=11),
+    W.river(n_target=30_000, workers=1)])
+def test_mesh_matches_oracle_counts_and_geometry(ctx, case):
+    """Edge counts, E = (3T + B)/2, and per-cell area / inscribed radius equal
+    the oracle's (two independent implementations of sec. 3.1 geometry)."""
+    S.swe_set_mesh(ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
+    info = S.swe_mesh_info(ctx)
+    o = O.Oracle(case)
+    oc = o.counts()
+    assert info["n_cells"] == oc["n_cells"]
+    assert info["n_edges"] == oc["n_edges"]
+    assert info["n_boundary_edges"] == oc["n_bnd_edges"]
+    assert 2 * info["n_edges"] == 3 * info["n_cells"] + info[
+        "n_boundary_edges"]
+    area, inr = S.swe_get_geometry(ctx)
+    oa, oi, _ = o.geometry()
+    assert np.array_equal(area, oa) and np.array_equal(inr, oi)
+    assert info["min_inradius"] == oi.min()
+    assert abs(info["total_area"] - math.fsum(oa)) < 1e-9 * info["total_area"]
+    nb = info["n_blocks"]
+    assert nb == -(-info["n_cells"] // info["block_cells"])
+    assert info["n_block_edges"] >= info["n_edges"]
+    assert info["max_block_edges"] <= 3 * info["block_cells"]
+
+
+def test_cell_order_is_a_permutation_that_restores_locality(ctx):
+    case = W.river(n_target=40_000, workers=1)       # cells shuffled
+    S.swe_set_mesh(ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
+    perm = S.swe_get_cell_order(ctx)
+    assert np.array_equal(np.sort(perm), np.arange(case.n_cells))
+    e = O.Oracle(case).edges()
+    inner = e["right"] >= 0
+    gap_user = np.abs(e["left"][inner] - e["right"][inner]).mean()
+    gap_int = np.abs(perm[e["left"][inner]] - perm[e["right"][inner]]).mean()
+    assert gap_int < 0.02 * gap_user
+    info = S.swe_mesh_info(ctx)
+    # compact blocks: few edges are duplicated on block borders
+    assert info["n_block_edges"] < 1.25 * info["n_edges"]
+
+
+def test_reorder_off_keeps_user_order(ctx):
+    case = W.bumps_canal(nx=20, ny=10)
+    p = S.swe_default_params()
+    p.reorder = 0
+    S.swe_set_params(ctx, p)
+    S.swe_set_mesh(ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
+    assert np.array_equal(S.swe_get_cell_order(ctx), np.arange(case.n_cells))
+
+
+def two_triangles():
+    xy = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], float)
+    tri = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    return xy, tri
+
+
+@pytest.mark.parametrize("kind", ["degenerate", "range", "nonmanifold",
+                                  "overlap", "segment", "dupseg", "tag",
+                                  "repeat", "nan"])
+def test_mesh_errors(ctx, kind):
+    xy, tri = two_triangles()
+    bnd = tag = None
+    if kind == "degenerate":
+        xy = np.vstack([xy, [2.0, 0.0]])
+        tri = np.vstack([tri, [0, 1, 4]]).astype(np.int32)
+    elif kind == "range":
+        tri[0, 2] = 9
+    elif kind == "nonmanifold":
+        xy = np.vstack([xy, [2, 0.5]])
+        tri = np.vstack([tri, [0, 2, 4]]).astype(np.int32)
+    elif kind == "overlap":
+        xy = np.array([[0, 0], [1, 0], [1, 1], [0.2, 0.5]], float)
+        tri = np.array([[0, 1, 2], [0, 1, 3]], np.int32)
+    elif kind == "segment":
+        bnd, tag = np.array([[0, 2]], np.int32), np.array([1], np.int32)
+    elif kind == "dupseg":
+        bnd = np.array([[0, 1], [1, 0]], np.int32)
+        tag = np.array([1, 2], np.int32)
+    elif kind == "tag":
+        bnd, tag = np.array([[0, 1]], np.int32), np.array([5000], np.int32)
+    elif kind == "repeat":
+        tri[1] = [0, 2, 2]
+    elif kind == "nan":
+        xy[3, 0] = np.nan
+    with pytest.raises(S.SweError) as e:
+        S.swe_set_mesh(ctx, xy, tri, bnd, tag)
+    assert e.value.status == S.SWE_EMESH
+    assert S.swe_last_error(ctx)
+
+
+def test_calls_before_mesh_are_not_ready(ctx):
+    with pytest.raises(S.SweError) as e:
+        S.swe_advance(ctx, 1)
+    assert e.value.status == S.SWE_ENOTREADY
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("h", -1.0, S.SWE_ESTATE), ("h", np.nan, S.SWE_ESTATE),
+    ("hu", np.inf, S.SWE_ESTATE), ("z", np.nan, S.SWE_ESTATE),
+    ("manning", -0.01, S.SWE_ESTATE)])
+def test_bad_fields_are_rejected_on_the_host(ctx, field, value, status):
+    xy, tri = two_triangles()
+    S.swe_set_mesh(ctx, xy, tri)
+    v = {k: np.zeros(2) for k in ("h", "hu", "hv", "z", "manning")}
+    v["h"][:] = 1.0
+    v[field][1] = value
+    with pytest.raises(S.SweError) as e:
+        if field in ("h", "hu"):
+            S.swe_set_state(ctx, v["h"], v["hu"], v["hv"])
+        elif field == "z":
+            S.swe_set_bathymetry(ctx, v["z"])
+        else:
+            S.swe_set_manning(ctx, v["manning"])
+    assert e.value.status == status
+
+
+@pytest.mark.parametrize("name,value", [("g", 0.0), ("cfl", -1.0),
+                                        ("h_dry", -1e-3), ("dt_max", 0.0),
+                                        ("check_every", 0),
+                                        ("block_cells", 100),
+                                        ("reorder", 2), ("reserved", 1)])
+def test_bad_params_are_rejected(ctx, name, value):
+    p = S.swe_default_params()
+    setattr(p, name, value)
+    with pytest.raises(S.SweError) as e:
+        S.swe_set_params(ctx, p)
+    assert e.value.status == S.SWE_EINVAL
+
+
+@pytest.mark.parametrize("tag,kind,value", [(-1, 0, 0.0), (1024, 0, 0.0),
+                                            (1, 7, 0.0), (1, 2, np.inf),
+                                            (1, 3, -1.0)])
+def test_bad_boundary_conditions_are_rejected(ctx, tag, kind, value):
+    with pytest.raises(S.SweError) as e:
+        S.swe_set_bc(ctx, tag, kind, value)
+    assert e.value.status == S.SWE_EINVAL
+
+
+def test_workspace_size_and_binding_checks(ctx):
+    xy, tri = two_triangles()
+    S.swe_set_mesh(ctx, xy, tri)
+    nb = S.swe_workspace_bytes(ctx)
+    assert nb > 0 and nb % 256 == 0
+    with pytest.raises(S.SweError) as e:
+        S.swe_bind_workspace(ctx, 256, nb - 256)
+    assert e.value.status == S.SWE_ENOMEM
+    with pytest.raises(S.SweError) as e:
+        S.swe_bind_workspace(ctx, 257, nb)
+    assert e.value.status == S.SWE_EINVAL

@@ -1,0 +1,216 @@
+"""Parity of the HIP path (through the C interface) with the FP64 oracle.
+
+Tolerances: relative L-infinity per field, max|X_gpu - X_ora| / max|X_ora|,
+at most 1e-12 after one step and 1e-9 after a full run. Sizes here span many
+blocks with a ragged last block; the full-size workloads are in
+test_gpu_fullsize.py.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ONE_STEP = 1e-12
+FULL_RUN = 1e-9
+
+
+def rel_linf(a, b):
+    d = float(np.max(np.abs(a - b))) if a.size else 0.0
+    s = float(np.max(np.abs(b))) if b.size else 0.0
+    return d / max(s, 1e-300)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def solver(case, **kw):
+    from paper_2010_14416_amd import Solver
+    return Solver(case, device=0, **kw)
+
+
+def compare(case, steps, t_end=math.inf, tol=ONE_STEP, **kw):
+    say(f"[parity] {case.name} cells={case.n_cells} steps={steps} "
+        f"t_end={t_end} {kw}")
+    s = solver(case, **kw)
+    n_gpu, t_gpu = s.advance(steps, t_end, want_time=True)
+    hg, hug, hvg = s.state()
+    o = O.Oracle(case)
+    n_ora, t_ora = o.run(steps, t_end)
+    ho, huo, hvo = o.state()
+    errs = [rel_linf(hg, ho), rel_linf(hug, huo), rel_linf(hvg, hvo)]
+    say(f"  rel Linf h={errs[0]:.3e} hu={errs[1]:.3e} hv={errs[2]:.3e} "
+        f"steps gpu={n_gpu} ora={n_ora} t gpu={t_gpu!r} ora={t_ora!r}")
+    assert n_gpu == n_ora
+    assert abs(t_gpu - t_ora) <= 1e-12 * max(1.0, abs(t_ora))
+    assert max(errs) <= tol, errs
+    return s, o
+
+
+def test_dam_break_one_step():
+    compare(W.dam_break_canal(), 1)
+
+
+def test_dam_break_full_run_to_5s():
+    case = W.dam_break_canal()
+    s, o = compare(case, 10**6, case.t_end, FULL_RUN)
+    t, last_dt, step = s.time()
+    assert t == 5.0 and step == o.clock()["step"]
+
+
+def test_bumps_dry_bed_one_step_and_run():
+    case = W.bumps_canal(nx=200, ny=101, steps=300)       # ragged last block
+    assert case.n_cells % 256 != 0
+    compare(case, 1)
+    s, o = compare(case, case.steps, tol=FULL_RUN)
+    m_gpu, led_gpu, wet_gpu = s.diagnostics()
+    area, _, _ = o.geometry()
+    h, _, _ = o.state()
+    m_ora = math.fsum(area * h)
+    assert abs(m_gpu - m_ora) <= 1e-12 * m_ora
+    assert abs(led_gpu - o.clock()["ledger"]) <= 1e-9 * max(
+        1e-300, abs(o.clock()["ledger"])) + 1e-15 * m_ora
+    assert wet_gpu == int(np.sum(h > case.h_dry))
+
+
+def test_river_inflow_fixed_stage_wet_dry():
+    case = W.river(n_target=120_000, workers=4, steps=200)
+    compare(case, 1)
+    compare(case, case.steps, tol=FULL_RUN)
+
+
+def test_lake_at_rest_gpu():
+    case = W.lake_at_rest(nx=100, ny=40)
+    s = solver(case)
+    s.advance(2000)
+    h, hu, hv = s.state()
+    wet = h > 0
+    assert np.max(np.abs(hu)) <= 1e-12 and np.max(np.abs(hv)) <= 1e-12
+    assert np.max(np.abs(h[wet] + case.z[wet] - 0.12)) <= 1e-12
+
+
+@pytest.mark.parametrize("block_cells,reorder", [(64, True), (128, True),
+                                                 (512, True), (256, False)])
+def test_blocking_and_order_do_not_change_bits(block_cells, reorder):
+    """Per-cell arithmetic is independent of how cells are grouped into
+    blocks and ordered: results are bitwise those of the default layout."""
+    case = W.bumps_canal(nx=90, ny=31, lx=30.0, ly=10.0, x_dam=15.0)
+    ref = solver(case)
+    ref.advance(60)
+    a = ref.state()
+    s = solver(case, block_cells=block_cells, reorder=reorder)
+    s.advance(60)
+    b = s.state()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_user_cell_permutation_gives_identical_bits():
+    case = W.bumps_canal(nx=90, ny=31, lx=30.0, ly=10.0, x_dam=15.0)
+    perm = np.random.default_rng(1).permutation(case.n_cells)
+    p = case.copy()
+    p.tri, p.z, p.manning = case.tri[perm], case.z[perm], case.manning[perm]
+    p.h, p.hu, p.hv = case.h[perm], case.hu[perm], case.hv[perm]
+    a = solver(case)
+    a.advance(40)
+    b = solver(p)
+    b.advance(40)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x[perm], y)
+
+
+def test_run_to_run_determinism():
+    case = W.river(n_target=50_000, workers=4)
+    a = solver(case)
+    a.advance(50)
+    b = solver(case)
+    b.advance(50)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+
+
+def test_device_tensors_workspace_and_stream_kinds():
+    import torch
+    case = W.bumps_canal(nx=60, ny=20, lx=30.0, ly=10.0, x_dam=15.0)
+    dev = torch.device("cuda", 0)
+    a = solver(case, workspace="library", stream=None)
+    a.advance(30)
+    ha = a.state()
+    b = solver(case)
+    # device-tensor state in, 30 steps, device-tensor state out
+    t = [torch.tensor(x, dtype=torch.float64, device=dev)
+         for x in (case.h, case.hu, case.hv)]
+    b.set_state(*t)
+    b.advance(30)
+    out = [torch.empty(case.n_cells, dtype=torch.float64, device=dev)
+           for _ in range(3)]
+    b.state(out)
+    for x, y in zip(ha, out):
+        assert np.array_equal(x, y.cpu().numpy())
+
+
+def test_resume_is_bitwise():
+    case = W.bumps_canal(nx=60, ny=20, lx=30.0, ly=10.0, x_dam=15.0)
+    a = solver(case)
+    a.advance(50)
+    full = a.state()
+    b = solver(case)
+    b.advance(20)
+    h, hu, hv = b.state()
+    t, _, step = b.time()
+    c = solver(case)
+    c.set_state(h, hu, hv)
+    from paper_2010_14416_amd import swe as S
+    S.swe_set_time(c.ctx, t, step)
+    c.advance(30)
+    for x, y in zip(full, c.state()):
+        assert np.array_equal(x, y)
+    assert c.time()[2] == a.time()[2]
+
+
+def test_t_end_stops_exactly_and_counts_steps():
+    case = W.dam_break_canal()
+    from paper_2010_14416_amd import swe as S
+    s = solver(case, params={"check_every": 7})
+    n, t = s.advance(10**6, 1.2345)
+    o = O.Oracle(case)
+    n2, t2 = o.run(10**6, 1.2345)
+    assert t == 1.2345 and n == n2
+    # already at t_end: nothing to do
+    n3, t3 = s.advance(10, 1.2345)
+    assert n3 == 0 and t3 == 1.2345
+    assert S.swe_get_time(s.ctx)[0] == 1.2345
+
+
+def test_all_dry_without_bound_reports_numeric_error():
+    from paper_2010_14416_amd import swe as S
+    case = W.dam_break_canal(nx=10, ny=2, lx=10.0, ly=2.0, h_left=0.0,
+                             h_right=0.0)
+    s = solver(case)
+    with pytest.raises(S.SweError) as e:
+        s.advance(1, want_time=True)
+    assert e.value.status == S.SWE_ENUMERIC
+    # with an end time the step is bounded
+    s2 = solver(case)
+    n, t = s2.advance(5, 0.5)
+    assert t == 0.5 and n == 1
+
+
+def test_tiny_meshes():
+    xy = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], float)
+    tri = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    case = W.Case(name="two-triangles", xy=xy, tri=tri,
+                  bnd=np.zeros((0, 2), np.int32),
+                  bnd_tag=np.zeros(0, np.int32), bc={},
+                  z=np.array([0.0, 0.1]), manning=np.array([0.02, 0.03]),
+                  h=np.array([1.0, 0.2]), hu=np.array([0.1, 0.0]),
+                  hv=np.array([0.0, -0.05]))
+    compare(case, 1)
+    compare(case, 40, tol=FULL_RUN)
