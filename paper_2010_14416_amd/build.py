@@ -27,6 +27,7 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=off",
+              "-fopenmp",
               "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include"]
 
 
@@ -49,7 +50,7 @@ def build(verbose: bool = True) -> str:
         objs.append(obj)
     tmp = LIB + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o",
-          tmp, f"-L{ROCM}/lib", "-lamdhip64"])
+          tmp, f"-L{ROCM}/lib", "-lamdhip64", "-lgomp"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -49,6 +49,24 @@ uint32_t hilbert_index(uint32_t x, uint32_t y)
     return d;
 }
 
+// Stable LSD radix sort of 64-bit keys on bits [lo_bit, 64), 16 bits per
+// pass; keys equal on those bits keep their input order.
+void radix_sort_u64(std::vector<uint64_t> &a, int lo_bit)
+{
+    std::vector<uint64_t> tmp(a.size());
+    for (int shift = lo_bit; shift < 64; shift += 16) {
+        std::vector<size_t> cnt(65537, 0);
+        for (uint64_t v : a) ++cnt[((v >> shift) & 0xffffu) + 1];
+        bool trivial = false;
+        for (size_t d = 0; d < 65536; ++d)
+            if (cnt[d + 1] == a.size()) trivial = true;
+        if (trivial) continue;
+        for (size_t d = 0; d < 65536; ++d) cnt[d + 1] += cnt[d];
+        for (uint64_t v : a) tmp[cnt[(v >> shift) & 0xffffu]++] = v;
+        a.swap(tmp);
+    }
+}
+
 }  // namespace
 
 bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
@@ -62,7 +80,7 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
         err = "mesh needs at least 3 nodes and 1 triangle";
         return false;
     }
-    if (nn > INT32_MAX || nc > INT32_MAX / 3) {
+    if (nn > INT32_MAX - 1 || nc > INT32_MAX / 3) {
         err = "mesh too large for 32-bit indices";
         return false;
     }
@@ -76,25 +94,23 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
     // ---- orientation, area, inscribed radius (user order)
     std::vector<int32_t> tri(3 * nc);
     std::vector<double> area(nc), inr(nc);
+    int64_t bad_cell = INT64_MAX;
+#pragma omp parallel for schedule(static) reduction(min : bad_cell)
     for (int64_t c = 0; c < nc; ++c) {
         int32_t v0 = tri_in[3 * c], v1 = tri_in[3 * c + 1],
                 v2 = tri_in[3 * c + 2];
-        if (v0 < 0 || v1 < 0 || v2 < 0 || v0 >= nn || v1 >= nn || v2 >= nn) {
-            err = fmt("triangle %lld references a node out of range",
-                      (long long)c);
-            return false;
-        }
-        if (v0 == v1 || v1 == v2 || v0 == v2) {
-            err = fmt("triangle %lld repeats a node", (long long)c);
-            return false;
+        if (v0 < 0 || v1 < 0 || v2 < 0 || v0 >= nn || v1 >= nn || v2 >= nn ||
+            v0 == v1 || v1 == v2 || v0 == v2) {
+            bad_cell = std::min(bad_cell, c);
+            continue;
         }
         const double x0 = xy[2 * v0], y0 = xy[2 * v0 + 1];
         const double x1 = xy[2 * v1], y1 = xy[2 * v1 + 1];
         const double x2 = xy[2 * v2], y2 = xy[2 * v2 + 1];
         double twice = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0);
         if (twice == 0.0) {
-            err = fmt("triangle %lld has zero area", (long long)c);
-            return false;
+            bad_cell = std::min(bad_cell, c);
+            continue;
         }
         if (twice < 0.0) {
             std::swap(v1, v2);
@@ -113,24 +129,48 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
         }
         inr[c] = 2.0 * area[c] / per;
     }
+    if (bad_cell != INT64_MAX) {
+        const int64_t c = bad_cell;
+        const int32_t v0 = tri_in[3 * c], v1 = tri_in[3 * c + 1],
+                      v2 = tri_in[3 * c + 2];
+        if (v0 < 0 || v1 < 0 || v2 < 0 || v0 >= nn || v1 >= nn || v2 >= nn)
+            err = fmt("triangle %lld references a node out of range",
+                      (long long)c);
+        else if (v0 == v1 || v1 == v2 || v0 == v2)
+            err = fmt("triangle %lld repeats a node", (long long)c);
+        else
+            err = fmt("triangle %lld has zero area", (long long)c);
+        return false;
+    }
 
     // ---- unique edges: bucket the 3 nc sides by their lower node, then
-    //      sort each (short) bucket by the higher node
+    //      sort each (short) bucket by (higher node, side)
     std::vector<int64_t> start(nn + 1, 0);
-    for (int64_t c = 0; c < nc; ++c)
-        for (int k = 0; k < 3; ++k) {
+    {
+        std::vector<int32_t> cnt(nn, 0);
+#pragma omp parallel for schedule(static)
+        for (int64_t s = 0; s < 3 * nc; ++s) {
+            const int64_t c = s / 3;
+            const int k = int(s % 3);
             const int32_t p = tri[3 * c + k], q = tri[3 * c + (k + 1) % 3];
-            ++start[std::min(p, q) + 1];
+#pragma omp atomic
+            cnt[std::min(p, q)] += 1;
         }
-    for (int64_t n = 0; n < nn; ++n) start[n + 1] += start[n];
+        for (int64_t n = 0; n < nn; ++n) start[n + 1] = start[n] + cnt[n];
+    }
     std::vector<int32_t> bucket(3 * nc);
     {
         std::vector<int64_t> fill(start.begin(), start.end() - 1);
-        for (int64_t c = 0; c < nc; ++c)
-            for (int k = 0; k < 3; ++k) {
-                const int32_t p = tri[3 * c + k], q = tri[3 * c + (k + 1) % 3];
-                bucket[fill[std::min(p, q)]++] = int32_t(3 * c + k);
-            }
+#pragma omp parallel for schedule(static)
+        for (int64_t s = 0; s < 3 * nc; ++s) {
+            const int64_t c = s / 3;
+            const int k = int(s % 3);
+            const int32_t p = tri[3 * c + k], q = tri[3 * c + (k + 1) % 3];
+            int64_t at;
+#pragma omp atomic capture
+            at = fill[std::min(p, q)]++;
+            bucket[at] = int32_t(s);
+        }
     }
     auto hi_node = [&](int32_t s) {
         const int64_t c = s / 3;
@@ -169,68 +209,93 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
         }
     }
 
-    // edge table (global edge ids in (lower node, higher node) order)
-    std::vector<int32_t> e_left, e_right, e_tag;   // user cells / -1
-    std::vector<int8_t> e_lk;                      // left cell's local side
-    std::vector<int32_t> side_edge(3 * nc);        // side -> edge
-    e_left.reserve(3 * nc / 2 + nn);
-    int64_t nb = 0;
-    std::vector<int32_t> tmp;
+    // pass 1: sort each bucket, validate, count its unique edges
+    std::vector<int64_t> estart(nn + 1, 0);
+    int64_t bad_node = INT64_MAX;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(min : bad_node)
     for (int64_t a = 0; a < nn; ++a) {
-        const int64_t s0 = start[a], s1 = start[a + 1];
-        tmp.assign(bucket.begin() + s0, bucket.begin() + s1);
-        std::sort(tmp.begin(), tmp.end(), [&](int32_t u, int32_t v) {
+        int32_t *b0 = bucket.data() + start[a];
+        int32_t *b1 = bucket.data() + start[a + 1];
+        std::sort(b0, b1, [&](int32_t u, int32_t v) {
             const int32_t bu = hi_node(u), bv = hi_node(v);
             return bu != bv ? bu < bv : u < v;
         });
-        for (size_t i = 0; i < tmp.size();) {
-            size_t j = i + 1;
-            while (j < tmp.size() && hi_node(tmp[j]) == hi_node(tmp[i])) ++j;
-            const int32_t b = hi_node(tmp[i]);
+        int64_t ne_a = 0;
+        for (int32_t *i = b0; i < b1;) {
+            int32_t *j = i + 1;
+            while (j < b1 && hi_node(*j) == hi_node(*i)) ++j;
+            if (j - i > 2 || (j - i == 2 && fwd(i[0]) == fwd(i[1])))
+                bad_node = std::min(bad_node, a);
+            ++ne_a;
+            i = j;
+        }
+        estart[a + 1] = ne_a;
+    }
+    if (bad_node != INT64_MAX) {
+        const int64_t a = bad_node;
+        for (int64_t i = start[a]; i < start[a + 1];) {
+            int64_t j = i + 1;
+            while (j < start[a + 1] && hi_node(bucket[j]) == hi_node(bucket[i]))
+                ++j;
+            const int32_t b = hi_node(bucket[i]);
             if (j - i > 2) {
                 err = fmt("edge (%lld,%d) is shared by more than two triangles",
                           (long long)a, b);
                 return false;
             }
-            const int32_t e = int32_t(e_left.size());
+            if (j - i == 2 && fwd(bucket[i]) == fwd(bucket[i + 1])) {
+                err = fmt("triangles %d and %d overlap along edge (%lld,%d)",
+                          bucket[i] / 3, bucket[i + 1] / 3, (long long)a, b);
+                return false;
+            }
+            i = j;
+        }
+    }
+    for (int64_t a = 0; a < nn; ++a) estart[a + 1] += estart[a];
+    const int64_t ne = estart[nn];
+    if (ne > INT32_MAX) {
+        err = "mesh too large for 32-bit edge indices";
+        return false;
+    }
+
+    // pass 2: edge table in (lower node, higher node) order
+    std::vector<int32_t> e_left(ne), e_right(ne), e_tag(ne);
+    std::vector<int8_t> e_lk(ne);
+    std::vector<int32_t> side_edge(3 * nc);
+    int64_t nb = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : nb)
+    for (int64_t a = 0; a < nn; ++a) {
+        int64_t e = estart[a];
+        for (int64_t i = start[a]; i < start[a + 1]; ++e) {
+            int64_t j = i + 1;
+            while (j < start[a + 1] && hi_node(bucket[j]) == hi_node(bucket[i]))
+                ++j;
+            const int32_t b = hi_node(bucket[i]);
             if (j - i == 2) {
-                if (fwd(tmp[i]) == fwd(tmp[i + 1])) {
-                    err = fmt("triangles %d and %d overlap along edge "
-                              "(%lld,%d)", tmp[i] / 3, tmp[i + 1] / 3,
-                              (long long)a, b);
-                    return false;
-                }
-                const int32_t l = fwd(tmp[i]) ? tmp[i] : tmp[i + 1];
-                const int32_t r = fwd(tmp[i]) ? tmp[i + 1] : tmp[i];
-                e_left.push_back(l / 3);
-                e_lk.push_back(int8_t(l % 3));
-                e_right.push_back(r / 3);
-                e_tag.push_back(0);
-                side_edge[l] = e;
-                side_edge[r] = e;
+                const int32_t l = fwd(bucket[i]) ? bucket[i] : bucket[i + 1];
+                const int32_t r = fwd(bucket[i]) ? bucket[i + 1] : bucket[i];
+                e_left[e] = l / 3;
+                e_lk[e] = int8_t(l % 3);
+                e_right[e] = r / 3;
+                e_tag[e] = 0;
+                side_edge[l] = int32_t(e);
+                side_edge[r] = int32_t(e);
             } else {
-                const int32_t l = tmp[i];
+                const int32_t l = bucket[i];
                 int32_t tag = 0;
                 for (int64_t k = sstart[a]; k < sstart[a + 1]; ++k) {
                     const int32_t s = sbucket[k];
-                    const int32_t hb = std::max(bnd_nodes[2 * s],
-                                                bnd_nodes[2 * s + 1]);
-                    if (hb == b) {
-                        if (sused[s]) {
-                            err = fmt("boundary segment (%lld,%d) listed twice",
-                                      (long long)a, b);
-                            return false;
-                        }
+                    if (std::max(bnd_nodes[2 * s], bnd_nodes[2 * s + 1]) == b) {
                         sused[s] = 1;
                         tag = bnd_tag[s];
                         break;
                     }
                 }
-                e_left.push_back(l / 3);
-                e_lk.push_back(int8_t(l % 3));
-                e_right.push_back(-1);
-                e_tag.push_back(tag);
-                side_edge[l] = e;
+                e_left[e] = l / 3;
+                e_lk[e] = int8_t(l % 3);
+                e_right[e] = -1;
+                e_tag[e] = tag;
+                side_edge[l] = int32_t(e);
                 ++nb;
             }
             i = j;
@@ -254,11 +319,13 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
                             "of the mesh", p, q);
             return false;
         }
-    const int64_t ne = int64_t(e_left.size());
+    std::vector<int64_t>().swap(start);
+    std::vector<int32_t>().swap(bucket);
 
     // edge geometry from the left cell's counter-clockwise traversal p -> q:
     // L = |q - p|, outward normal (dy, -dx) / L
     std::vector<double> enx(ne), eny(ne), elen(ne);
+#pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < ne; ++e) {
         const int64_t c = e_left[e];
         const int k = e_lk[e];
@@ -277,7 +344,6 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
     // ---- internal cell order: Hilbert curve through the centroids, on a
     //      square lattice covering the bounding box (ties keep user order)
     std::vector<int32_t> order(nc);
-    std::iota(order.begin(), order.end(), 0);
     if (reorder && nc > 1) {
         double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY,
                ymax = -INFINITY;
@@ -290,6 +356,7 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
         const double ext = std::max(xmax - xmin, ymax - ymin);
         const double sc = ext > 0 ? 65535.0 / ext : 0.0;
         std::vector<uint64_t> key(nc);
+#pragma omp parallel for schedule(static)
         for (int64_t c = 0; c < nc; ++c) {
             double cx = 0, cy = 0;
             for (int k = 0; k < 3; ++k) {
@@ -298,15 +365,22 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
             }
             cx /= 3.0;
             cy /= 3.0;
-            const uint32_t qx = uint32_t(std::min(65535.0, std::max(0.0, (cx - xmin) * sc)));
-            const uint32_t qy = uint32_t(std::min(65535.0, std::max(0.0, (cy - ymin) * sc)));
+            const uint32_t qx = uint32_t(
+                std::min(65535.0, std::max(0.0, (cx - xmin) * sc)));
+            const uint32_t qy = uint32_t(
+                std::min(65535.0, std::max(0.0, (cy - ymin) * sc)));
             key[c] = (uint64_t(hilbert_index(qx, qy)) << 32) | uint64_t(c);
         }
-        std::sort(key.begin(), key.end());
-        for (int64_t i = 0; i < nc; ++i) order[i] = int32_t(key[i] & 0xffffffffu);
+        radix_sort_u64(key, 32);   // by curve index; ties in user order
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < nc; ++i)
+            order[i] = int32_t(key[i] & 0xffffffffu);
+    } else {
+        std::iota(order.begin(), order.end(), 0);
     }
     M.user_of_internal = order;
     M.internal_of_user.assign(nc, 0);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < nc; ++i) M.internal_of_user[order[i]] = int32_t(i);
 
     M.n_nodes = nn;
@@ -316,86 +390,127 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
     M.area.resize(nc);
     M.inv_area.resize(nc);
     M.inradius.resize(nc);
-    M.min_inradius = INFINITY;
-    M.total_area = 0.0;
+    double rmin = INFINITY;
+#pragma omp parallel for schedule(static) reduction(min : rmin)
     for (int64_t i = 0; i < nc; ++i) {
         const int32_t u = order[i];
         M.area[i] = area[u];
         M.inv_area[i] = 1.0 / area[u];
         M.inradius[i] = inr[u];
-        M.min_inradius = std::min(M.min_inradius, inr[u]);
-        M.total_area += area[u];
+        rmin = std::min(rmin, inr[u]);
     }
+    M.min_inradius = rmin;
+    M.total_area = 0.0;
+    for (int64_t i = 0; i < nc; ++i) M.total_area += M.area[i];
 
     // ---- blocks of block_cells consecutive internal cells and their edges:
     //      edges with both cells in the block first, then edges to another
-    //      block, then boundary edges; each group in order of first use
+    //      block, then boundary edges; each group in order of first use (an
+    //      edge inside the block is first used by its lower-numbered cell)
     const int32_t B = block_cells;
     const int64_t nblk = (nc + B - 1) / B;
     M.block_cells = B;
     M.n_blocks = int32_t(nblk);
     M.blk_cell.resize(nblk + 1);
-    M.blk_edge.resize(nblk + 1);
+    M.blk_edge.assign(nblk + 1, 0);
     M.slots.assign(nc, 0);
-    std::vector<int32_t> stamp(ne, -1), slot_of(ne, 0);
-    std::vector<int32_t> inner, halo, bnd;
-    M.be_left.reserve(size_t(ne * 1.2) + 16);
+    const std::vector<int32_t> &iou = M.internal_of_user;
+    // edge and neighbour (internal index, -1 on the boundary) of side k of
+    // internal cell i, gathered once in internal order
+    std::vector<int32_t> side_e(3 * nc), side_nb(3 * nc);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nc; ++i) {
+        const int32_t u = order[i];
+        for (int k = 0; k < 3; ++k) {
+            const int32_t e = side_edge[3 * int64_t(u) + k];
+            side_e[3 * i + k] = e;
+            side_nb[3 * i + k] =
+                e_right[e] < 0 ? -1
+                               : iou[e_left[e] == u ? e_right[e] : e_left[e]];
+        }
+    }
+    auto other = [&](int64_t i, int k, int32_t &e) -> int64_t {
+        e = side_e[3 * i + k];
+        return side_nb[3 * i + k];
+    };
     int32_t emax = 0;
+#pragma omp parallel for schedule(static) reduction(max : emax)
     for (int64_t b = 0; b < nblk; ++b) {
         const int64_t c0 = b * B, c1 = std::min<int64_t>(nc, c0 + B);
+        int32_t n = 0;
+        for (int64_t i = c0; i < c1; ++i)
+            for (int k = 0; k < 3; ++k) {
+                int32_t e;
+                const int64_t j = other(i, k, e);
+                if (j < 0 || j < c0 || j >= c1 || i < j) ++n;
+            }
         M.blk_cell[b] = int32_t(c0);
-        M.blk_edge[b] = int32_t(M.be_left.size());
-        inner.clear();
-        halo.clear();
-        bnd.clear();
-        for (int64_t i = c0; i < c1; ++i) {
-            const int32_t u = order[i];
-            for (int k = 0; k < 3; ++k) {
-                const int32_t e = side_edge[3 * int64_t(u) + k];
-                if (stamp[e] == int32_t(b)) continue;
-                stamp[e] = int32_t(b);
-                if (e_right[e] < 0) {
-                    bnd.push_back(e);
-                } else {
-                    const int64_t il = M.internal_of_user[e_left[e]];
-                    const int64_t ir = M.internal_of_user[e_right[e]];
-                    const bool both = il >= c0 && il < c1 && ir >= c0 && ir < c1;
-                    (both ? inner : halo).push_back(e);
-                }
-            }
-        }
-        const int32_t base = int32_t(M.be_left.size());
-        int32_t s = 0;
-        for (const auto *grp : {&inner, &halo, &bnd})
-            for (int32_t e : *grp) {
-                slot_of[e] = s++;
-                M.be_left.push_back(M.internal_of_user[e_left[e]]);
-                M.be_right.push_back(e_right[e] >= 0
-                                         ? M.internal_of_user[e_right[e]]
-                                         : -1 - e_tag[e]);
-                M.be_nx.push_back(enx[e]);
-                M.be_ny.push_back(eny[e]);
-                M.be_len.push_back(elen[e]);
-            }
-        emax = std::max(emax, s);
-        for (int64_t i = c0; i < c1; ++i) {
-            const int32_t u = order[i];
-            uint64_t pack = 0;
-            for (int k = 0; k < 3; ++k) {
-                const int32_t e = side_edge[3 * int64_t(u) + k];
-                const uint64_t right = (e_right[e] == u) ? 1u : 0u;
-                pack |= (uint64_t(slot_of[e]) | (right << 15)) << (16 * k);
-            }
-            M.slots[i] = pack;
-        }
-        (void)base;
+        M.blk_edge[b + 1] = n;
+        emax = std::max(emax, n);
     }
     M.blk_cell[nblk] = int32_t(nc);
-    M.blk_edge[nblk] = int32_t(M.be_left.size());
-    M.max_block_edges = emax;
+    for (int64_t b = 0; b < nblk; ++b) M.blk_edge[b + 1] += M.blk_edge[b];
     if (emax >= (1 << 15)) {
         err = "block edge list too long";
         return false;
+    }
+    M.max_block_edges = emax;
+    const int64_t nbe = M.blk_edge[nblk];
+    M.be_left.resize(nbe);
+    M.be_right.resize(nbe);
+    M.be_nx.resize(nbe);
+    M.be_ny.resize(nbe);
+    M.be_len.resize(nbe);
+    std::vector<int32_t> inner_slot(ne, 0);
+#pragma omp parallel
+    {
+        struct Use { int32_t e; int32_t side; };   // side = 3 * local + k
+        std::vector<Use> grp[3];
+        std::vector<int32_t> side_slot(3 * B);
+#pragma omp for schedule(static)
+        for (int64_t b = 0; b < nblk; ++b) {
+            const int64_t c0 = b * B, c1 = std::min<int64_t>(nc, c0 + B);
+            for (auto &g : grp) g.clear();
+            std::fill(side_slot.begin(), side_slot.end(), -1);
+            for (int64_t i = c0; i < c1; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    int32_t e;
+                    const int64_t j = other(i, k, e);
+                    const Use use{e, int32_t(3 * (i - c0) + k)};
+                    if (j < 0) grp[2].push_back(use);
+                    else if (j < c0 || j >= c1) grp[1].push_back(use);
+                    else if (i < j) grp[0].push_back(use);
+                }
+            int32_t s = 0;
+            int64_t at = M.blk_edge[b];
+            for (int g = 0; g < 3; ++g)
+                for (const Use &use : grp[g]) {
+                    const int32_t e = use.e;
+                    side_slot[use.side] = s;
+                    if (g == 0) inner_slot[e] = s;
+                    M.be_left[at] = iou[e_left[e]];
+                    M.be_right[at] = e_right[e] >= 0 ? iou[e_right[e]]
+                                                     : -1 - e_tag[e];
+                    M.be_nx[at] = enx[e];
+                    M.be_ny[at] = eny[e];
+                    M.be_len[at] = elen[e];
+                    ++at;
+                    ++s;
+                }
+            for (int64_t i = c0; i < c1; ++i) {
+                const int32_t u = order[i];
+                uint64_t pack = 0;
+                for (int k = 0; k < 3; ++k) {
+                    int32_t e;
+                    other(i, k, e);
+                    int32_t slot = side_slot[3 * (i - c0) + k];
+                    if (slot < 0) slot = inner_slot[e];
+                    const uint64_t right = (e_right[e] == u) ? 1u : 0u;
+                    pack |= (uint64_t(slot) | (right << 15)) << (16 * k);
+                }
+                M.slots[i] = pack;
+            }
+        }
     }
     return true;
 }

@@ -74,6 +74,14 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    # One HIP runtime per process: torch ships its own copy of the HIP and
+    # HSA runtimes under the same soname (libamdhip64.so.7). Importing torch
+    # first makes libswe.so bind to that copy instead of loading a second
+    # runtime from /opt/rocm, which could not open the device again.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with "
