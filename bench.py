@@ -77,6 +77,27 @@ def traffic_per_launch(workload_name, n_cells):
     return t.get("bytes_per_launch")
 
 
+def copy_bandwidth(mb, reps=5):
+    """A plain device-to-device copy of `mb` MiB (float64), the reference
+    kernel of known traffic: returns GB/s counting read + write bytes."""
+    import torch
+    n = mb * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(case, seconds, threads):
     import oracle
     o = oracle.Oracle(case, threads=threads)
@@ -104,10 +125,14 @@ def main():
                     choices=["river", "bumps", "canal"])
     ap.add_argument("--cells", type=int, default=13_000_000)
     ap.add_argument("--block-cells", type=int, default=256)
+    ap.add_argument("--block-threads", type=int, default=0,
+                    help="0: automatic (2 x block cells)")
     ap.add_argument("--workers", type=int,
                     default=min(16, os.cpu_count() or 1))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=2048,
+                    help="size of the reference copy (0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -124,7 +149,8 @@ def main():
     log(f"workload {case.name}: {case.n_cells} cells "
         f"({time.perf_counter() - t0:.1f} s to generate)")
     t0 = time.perf_counter()
-    s = Solver(case, device=0, block_cells=args.block_cells)
+    s = Solver(case, device=0, block_cells=args.block_cells,
+               params={"block_threads": args.block_threads})
     info = s.info()
     s.advance(1, want_time=True)          # device set-up + first step
     setup_s = time.perf_counter() - t0
@@ -144,6 +170,11 @@ def main():
     log(f"{args.steps} steps in {elapsed_ms:.2f} ms; t = {t_sim:.4f} s, "
         f"dt = {last_dt:.4g} s")
 
+    copy_gbs = None
+    if args.copy_mb > 0:
+        copy_gbs = copy_bandwidth(args.copy_mb)
+        log(f"reference copy of {args.copy_mb} MiB: {copy_gbs:.0f} GB/s")
+
     n = case.n_cells
     ms_per_step = elapsed_ms / args.steps
     value = n * args.steps / (elapsed_ms * 1e-3)
@@ -151,7 +182,8 @@ def main():
     achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS,
                     unit="GB/s", frac=achieved / PEAK_HBM_GBS,
-                    traffic=traffic_per_launch(case.name, n))
+                    traffic=traffic_per_launch(case.name, n),
+                    copy_gbs=copy_gbs)
 
     base = None
     if not args.no_cpu_baseline:
@@ -167,7 +199,9 @@ def main():
         higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f64", data="synthetic",
         config=dict(workload=desc, n_cells=n, n_edges=info["n_edges"],
-                    block_cells=info["block_cells"], setup_s=round(setup_s, 2),
+                    block_cells=info["block_cells"],
+                    block_threads=args.block_threads or
+                    2 * info["block_cells"], setup_s=round(setup_s, 2),
                     effective_gbs=achieved),
         roofline=roofline, cpu_baseline=base)
     print(json.dumps(out), flush=True)

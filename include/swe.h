@@ -74,11 +74,13 @@ typedef struct {
     double dt_max;         /* upper bound on the time step [s] > 0 (+inf)      */
     int32_t check_every;   /* steps between host polls of the device clock
                               when t_end is finite (64)                       */
-    int32_t block_cells;   /* cells per mesh block, 64..1024, a multiple of
-                              64 (256); takes effect at the next set_mesh    */
+    int32_t block_cells;   /* cells per mesh block: 64, 128, 256 or 512
+                              (256); takes effect at the next set_mesh       */
     int32_t reorder;       /* 1: space-filling-curve cell order (default);
                               0: keep the user order; next set_mesh           */
-    int32_t reserved;      /* must be 0                                       */
+    int32_t block_threads; /* threads per block: block_cells, 2*block_cells,
+                              or 0 = automatic (2*block_cells, so that the
+                              block's edges take one pass) (0)                */
 } swe_params;
 
 typedef struct {

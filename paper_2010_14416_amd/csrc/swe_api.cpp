@@ -360,7 +360,7 @@ swe_status swe_default_params(swe_params *p)
     p->check_every = 64;
     p->block_cells = 256;
     p->reorder = 1;
-    p->reserved = 0;
+    p->block_threads = 0;
     return SWE_OK;
 }
 
@@ -423,7 +423,10 @@ swe_status swe_set_params(swe_ctx *c, const swe_params *p)
         return fail(c, SWE_EINVAL, "block_cells must be 64, 128, 256 or 512");
     if (p->reorder != 0 && p->reorder != 1)
         return fail(c, SWE_EINVAL, "reorder must be 0 or 1");
-    if (p->reserved != 0) return fail(c, SWE_EINVAL, "reserved must be 0");
+    if (p->block_threads != 0 && p->block_threads != p->block_cells &&
+        p->block_threads != 2 * p->block_cells)
+        return fail(c, SWE_EINVAL,
+                    "block_threads must be 0, block_cells or 2*block_cells");
     const bool g_changed = p->g != c->params.g;
     const bool dt_changed = g_changed || p->h_dry != c->params.h_dry;
     c->params = *p;
@@ -688,6 +691,9 @@ swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
     a.t_end = t_end;
     a.n_blocks = m.n_blocks;
     a.emax = m.max_block_edges;
+    const int threads = c->params.block_threads == 0
+                            ? 2 * m.block_cells
+                            : c->params.block_threads;
     auto launch_n = [&](int64_t n) -> swe_status {
         for (int64_t k = 0; k < n; ++k) {
             const int b = c->cur_buf;
@@ -699,7 +705,8 @@ swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
             a.hv1 = c->d.hv[b ^ 1];
             a.cur = c->cur_slot;
             a.step_index = c->step_index;
-            hipError_t e = swe::launch_step(a, m.block_cells, c->stream);
+            hipError_t e = swe::launch_step(a, m.block_cells, threads,
+                                            c->stream);
             if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
             c->cur_buf ^= 1;
             c->cur_slot = (c->cur_slot + 1) % 3;

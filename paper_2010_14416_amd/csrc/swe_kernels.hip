@@ -213,7 +213,9 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <int NT>
+// NC cells per block, NT threads (NC or 2 NC): threads below NC own a cell;
+// all NT threads share the block's edges.
+template <int NC, int NT>
 __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
 {
     extern __shared__ double lds[];
@@ -221,10 +223,10 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
     __shared__ double red_sum[NT / 64];
     __shared__ unsigned red_bad[NT / 64];
     double *s_h = lds;
-    double *s_u = s_h + NT;
-    double *s_v = s_u + NT;
-    double *s_z = s_v + NT;
-    double *s_c = s_z + NT;   // 6 x emax: left contributions, then right
+    double *s_u = s_h + NC;
+    double *s_v = s_u + NC;
+    double *s_z = s_v + NC;
+    double *s_c = s_z + NC;   // 6 x emax: left contributions, then right
     const int emax = a.emax;
 
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
     }
 
     // stage this block's cells
-    const bool own = tid < nc;
+    const bool own = tid < NC && tid < nc;
     const int i = c0 + tid;
     double h = 0.0, hu = 0.0, hv = 0.0;
     if (own) {
@@ -588,25 +590,36 @@ size_t step_lds_bytes(int block_cells, int emax)
     return sizeof(double) * (4 * size_t(block_cells) + 6 * size_t(emax));
 }
 
-hipError_t launch_step(const StepArgs &a, int block_cells, hipStream_t s)
+namespace {
+template <int NC, int NT>
+void launch_one(const StepArgs &a, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((swe_step_kernel<NC, NT>), dim3(a.n_blocks), dim3(NT),
+                       lds, s, a);
+}
+}  // namespace
+
+hipError_t launch_step(const StepArgs &a, int block_cells, int threads,
+                       hipStream_t s)
 {
     const size_t lds = step_lds_bytes(block_cells, a.emax);
+    const bool twice = threads == 2 * block_cells;
+    if (!twice && threads != block_cells) return hipErrorInvalidValue;
     switch (block_cells) {
     case 64:
-        hipLaunchKernelGGL(swe_step_kernel<64>, dim3(a.n_blocks), dim3(64),
-                           lds, s, a);
+        twice ? launch_one<64, 128>(a, lds, s) : launch_one<64, 64>(a, lds, s);
         break;
     case 128:
-        hipLaunchKernelGGL(swe_step_kernel<128>, dim3(a.n_blocks), dim3(128),
-                           lds, s, a);
+        twice ? launch_one<128, 256>(a, lds, s)
+              : launch_one<128, 128>(a, lds, s);
         break;
     case 256:
-        hipLaunchKernelGGL(swe_step_kernel<256>, dim3(a.n_blocks), dim3(256),
-                           lds, s, a);
+        twice ? launch_one<256, 512>(a, lds, s)
+              : launch_one<256, 256>(a, lds, s);
         break;
     case 512:
-        hipLaunchKernelGGL(swe_step_kernel<512>, dim3(a.n_blocks), dim3(512),
-                           lds, s, a);
+        twice ? launch_one<512, 1024>(a, lds, s)
+              : launch_one<512, 512>(a, lds, s);
         break;
     default:
         return hipErrorInvalidValue;

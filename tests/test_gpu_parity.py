@@ -96,16 +96,20 @@ def test_lake_at_rest_gpu():
     assert np.max(np.abs(h[wet] + case.z[wet] - 0.12)) <= 1e-12
 
 
-@pytest.mark.parametrize("block_cells,reorder", [(64, True), (128, True),
-                                                 (512, True), (256, False)])
-def test_blocking_and_order_do_not_change_bits(block_cells, reorder):
+@pytest.mark.parametrize("block_cells,reorder,threads", [
+    (64, True, 0), (128, True, 0), (512, True, 0), (256, False, 0),
+    (256, True, 256), (64, True, 64), (512, True, 512)])
+def test_blocking_and_order_do_not_change_bits(block_cells, reorder,
+                                               threads):
     """Per-cell arithmetic is independent of how cells are grouped into
-    blocks and ordered: results are bitwise those of the default layout."""
+    blocks, ordered and spread over threads: results are bitwise those of
+    the default layout."""
     case = W.bumps_canal(nx=90, ny=31, lx=30.0, ly=10.0, x_dam=15.0)
     ref = solver(case)
     ref.advance(60)
     a = ref.state()
-    s = solver(case, block_cells=block_cells, reorder=reorder)
+    s = solver(case, block_cells=block_cells, reorder=reorder,
+               params={"block_threads": threads})
     s.advance(60)
     b = s.state()
     for x, y in zip(a, b):
