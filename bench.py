@@ -78,19 +78,21 @@ def traffic_per_launch(workload_name, n_cells):
 
 
 def copy_bandwidth(mb, reps=5):
-    """A plain device-to-device copy of `mb` MiB (float64), the reference
-    kernel of known traffic: returns GB/s counting read + write bytes."""
+    """Reference streaming kernel of known traffic: an elementwise pass that
+    reads `mb` MiB of float64 and writes `mb` MiB (b = -a, torch's neg
+    kernel; a plain copy may be routed to a DMA engine instead of a kernel).
+    Returns GB/s counting read + write bytes."""
     import torch
     n = mb * (1 << 20) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
+    torch.neg(a, out=b)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        b.copy_(a)
+        torch.neg(a, out=b)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -116,6 +118,58 @@ def cpu_baseline(case, seconds, threads):
                        f"setup excluded)")
 
 
+def _read_counter_csv(path, counter):
+    """Per-dispatch values of one counter from a rocprofv3 counter-collection
+    CSV: {kernel name: [KiB per dispatch, ...]}."""
+    import csv
+    out = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name", counter) != counter:
+                continue
+            out.setdefault(row["Kernel_Name"], []).append(
+                float(row["Counter_Value"]))
+    return out
+
+
+def pmc_summary(fetch_csv, write_csv, copy_mb, n_cells, out_path):
+    """Per-launch HBM traffic of the step kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by the ratio of
+    known to counted bytes of the reference streaming kernel."""
+    fetch = _read_counter_csv(fetch_csv, "FETCH_SIZE")
+    write = _read_counter_csv(write_csv, "WRITE_SIZE")
+
+    def pick(d, key):
+        ks = [k for k in d if key in k]
+        if not ks:
+            raise SystemExit(f"no dispatch of a kernel matching {key!r}")
+        vals = [v for k in ks for v in d[k]]
+        return sum(vals) / len(vals), len(vals)
+
+    known = copy_mb * (1 << 20)
+    cf, _ = pick(fetch, "neg_kernel")
+    cw, _ = pick(write, "neg_kernel")
+    sf, sw = known / (cf * 1024), known / (cw * 1024)
+    f_kib, nf = pick(fetch, "swe_step_kernel")
+    w_kib, nw = pick(write, "swe_step_kernel")
+    res = dict(kernel="swe_step_kernel", kernel_sha256=kernel_hash(),
+               n_cells=n_cells,
+               fetch_kib_per_launch=f_kib, write_kib_per_launch=w_kib,
+               dispatches=dict(fetch=nf, write=nw),
+               reference=dict(kernel="torch neg (elementwise, float64)",
+                              bytes_read=known, bytes_written=known,
+                              fetch_kib=cf, write_kib=cw,
+                              fetch_scale=sf, write_scale=sw),
+               fetch_bytes_per_launch=f_kib * 1024 * sf,
+               write_bytes_per_launch=w_kib * 1024 * sw)
+    res["bytes_per_launch"] = (res["fetch_bytes_per_launch"] +
+                               res["write_bytes_per_launch"])
+    res["bytes_per_cell"] = res["bytes_per_launch"] / n_cells
+    with open(out_path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,7 +187,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=2048,
                     help="size of the reference copy (0: skip)")
+    ap.add_argument("--sweep", default="",
+                    help="comma list of CELLSxTHREADS block shapes to time "
+                         "on the same mesh before the main run (stderr)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV",
+                                                        "WRITE_CSV"),
+                    help="write the step kernel's traffic summary from two "
+                         "rocprofv3 counter CSVs and exit (no GPU needed)")
+    ap.add_argument("--pmc-out", default=TRAFFIC_FILE)
+    ap.add_argument("--pmc-cells", type=int, default=13_004_176,
+                    help="cell count of the profiled workload")
     args = ap.parse_args()
+
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_mb,
+                    args.pmc_cells, args.pmc_out)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build's hot path has no "
@@ -148,6 +217,27 @@ def main():
     case, desc = make_case(args)
     log(f"workload {case.name}: {case.n_cells} cells "
         f"({time.perf_counter() - t0:.1f} s to generate)")
+    for shape in filter(None, args.sweep.split(",")):
+        bc, bt = (int(x) for x in shape.lower().split("x"))
+        sw = Solver(case, device=0, block_cells=bc,
+                    params={"block_threads": bt})
+        sw.advance(args.warmup + 1, want_time=True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(sw.stream)
+        sw.advance(args.steps)
+        e1.record(sw.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        sw.time()
+        log(f"sweep {bc}x{bt}: {ms:.4f} ms/step, "
+            f"{case.n_cells / (ms * 1e-3):.4e} cell-updates/s, "
+            f"{ALG_BYTES_PER_CELL * case.n_cells / (ms * 1e-3) / 1e9:.0f} "
+            f"GB/s algorithmic")
+        sw.close()
+        del sw
+
     t0 = time.perf_counter()
     s = Solver(case, device=0, block_cells=args.block_cells,
                params={"block_threads": args.block_threads})

@@ -23,6 +23,8 @@ ARCH = "gfx950"
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
+    # formulas round as written: no fused multiply-add contraction
+    "-ffp-contract=off",
     # no packed FP32 instructions (the step is FP64 throughout)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

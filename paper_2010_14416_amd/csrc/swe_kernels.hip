@@ -19,7 +19,14 @@
 //      the device without a host round trip.
 // State and geometry are FP64 structure-of-arrays, read once per step with
 // coalesced loads; edges on a block border are evaluated by both blocks.
+//
+// Arithmetic: every formula is evaluated as written, operation by operation,
+// with correctly rounded +, -, *, /, sqrt and no contraction into fused
+// multiply-adds, so that results are reproducible bit for bit from the
+// formulas (the only library function is cbrt, in the friction coefficient).
 #include <hip/hip_runtime.h>
+
+#pragma clang fp contract(off)
 
 #include <cfloat>
 #include <climits>
@@ -100,9 +107,8 @@ __device__ __forceinline__ void hllc(double g, double h_dry, double hL,
     } else {
         const double FL1 = qL * uL + 0.5 * g * hL * hL;
         const double FR1 = qR * uR + 0.5 * g * hR * hR;
-        const double inv = 1.0 / (SR - SL);
-        G0 = (SR * qL - SL * qR + SR * SL * (hR - hL)) * inv;
-        G1 = (SR * FL1 - SL * FR1 + SR * SL * (qR - qL)) * inv;
+        G0 = (SR * qL - SL * qR + SR * SL * (hR - hL)) / (SR - SL);
+        G1 = (SR * FL1 - SL * FR1 + SR * SL * (qR - qL)) / (SR - SL);
         G2 = G0 * (Ss >= 0.0 ? vL : vR);
     }
 }
@@ -331,8 +337,8 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
         }
         double hn = h, hun = hu, hvn = hv;
         if (dt > 0.0) {
-            const double ia = a.inv_area[i];
-            const double bh = R0 * ia, bx = R1 * ia, by = R2 * ia;
+            const double A = a.area[i];
+            const double bh = R0 / A, bx = R1 / A, by = R2 / A;
             const double dh = dt * bh;
             const double qn = sqrt(hu * hu + hv * hv);
             double dqx, dqy;
@@ -340,17 +346,20 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
                 // semi-implicit Manning: S_f = -c|q|q, c = g m^2 h^(-7/3);
                 // (I - dt/2 dS/dq) dq = dt (R_q/A + S_f) + dt/2 (dS/dh) dh
                 const double c = a.gm2[i] / (h * h * cbrt(h));
-                const double cq = c * qn;
-                const double iq = 1.0 / qn;
-                const double jh = (7.0 / 3.0) * cq / h;
-                const double m11 = 1.0 + 0.5 * dt * c * (qn + hu * hu * iq);
-                const double m12 = 0.5 * dt * c * hu * hv * iq;
-                const double m22 = 1.0 + 0.5 * dt * c * (qn + hv * hv * iq);
-                const double rx = dt * (bx - cq * hu) + 0.5 * dt * jh * hu * dh;
-                const double ry = dt * (by - cq * hv) + 0.5 * dt * jh * hv * dh;
-                const double idet = 1.0 / (m11 * m22 - m12 * m12);
-                dqx = (rx * m22 - m12 * ry) * idet;
-                dqy = (m11 * ry - m12 * rx) * idet;
+                const double sfx = -c * qn * hu, sfy = -c * qn * hv;
+                const double jhx = (7.0 / 3.0) * c * qn * hu / h;
+                const double jhy = (7.0 / 3.0) * c * qn * hv / h;
+                const double jxx = -c * (qn + hu * hu / qn);
+                const double jxy = -c * hu * hv / qn;
+                const double jyy = -c * (qn + hv * hv / qn);
+                const double m11 = 1.0 - 0.5 * dt * jxx;
+                const double m12 = -0.5 * dt * jxy;
+                const double m22 = 1.0 - 0.5 * dt * jyy;
+                const double rx = dt * (bx + sfx) + 0.5 * dt * jhx * dh;
+                const double ry = dt * (by + sfy) + 0.5 * dt * jhy * dh;
+                const double det = m11 * m22 - m12 * m12;
+                dqx = (rx * m22 - m12 * ry) / det;
+                dqy = (m11 * ry - m12 * rx) / det;
             } else {
                 dqx = dt * bx;
                 dqy = dt * by;
@@ -359,7 +368,7 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
             hun = hu + dqx;
             hvn = hv + dqy;
             if (hn < 0.0) {
-                clamp = -hn * a.area[i];
+                clamp = -A * hn;
                 hn = 0.0;
             }
             if (hn <= h_dry) {

@@ -81,7 +81,7 @@ def test_bumps_dry_bed_one_step_and_run():
 
 
 def test_river_inflow_fixed_stage_wet_dry():
-    case = W.river(n_target=120_000, workers=4, steps=200)
+    case = W.river(n_target=120_000, workers=1, steps=200)
     compare(case, 1)
     compare(case, case.steps, tol=FULL_RUN)
 
@@ -131,7 +131,7 @@ def test_user_cell_permutation_gives_identical_bits():
 
 
 def test_run_to_run_determinism():
-    case = W.river(n_target=50_000, workers=4)
+    case = W.river(n_target=50_000, workers=1)
     a = solver(case)
     a.advance(50)
     b = solver(case)
