@@ -81,6 +81,10 @@ typedef struct {
     int32_t block_threads; /* threads per block: block_cells, 2*block_cells,
                               or 0 = automatic (2*block_cells, so that the
                               block's edges take one pass) (0)                */
+    int32_t load_schedule; /* 0: issue every load of a block before its first
+                              barrier (default); 1: load per phase. Same
+                              results bit for bit; a tuning switch           */
+    int32_t reserved;      /* must be 0                                       */
 } swe_params;
 
 typedef struct {

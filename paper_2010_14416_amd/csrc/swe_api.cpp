@@ -361,6 +361,8 @@ swe_status swe_default_params(swe_params *p)
     p->block_cells = 256;
     p->reorder = 1;
     p->block_threads = 0;
+    p->load_schedule = 0;
+    p->reserved = 0;
     return SWE_OK;
 }
 
@@ -427,6 +429,9 @@ swe_status swe_set_params(swe_ctx *c, const swe_params *p)
         p->block_threads != 2 * p->block_cells)
         return fail(c, SWE_EINVAL,
                     "block_threads must be 0, block_cells or 2*block_cells");
+    if (p->load_schedule != 0 && p->load_schedule != 1)
+        return fail(c, SWE_EINVAL, "load_schedule must be 0 or 1");
+    if (p->reserved != 0) return fail(c, SWE_EINVAL, "reserved must be 0");
     const bool g_changed = p->g != c->params.g;
     const bool dt_changed = g_changed || p->h_dry != c->params.h_dry;
     c->params = *p;
@@ -706,6 +711,7 @@ swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
             a.cur = c->cur_slot;
             a.step_index = c->step_index;
             hipError_t e = swe::launch_step(a, m.block_cells, threads,
+                                            c->params.load_schedule,
                                             c->stream);
             if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
             c->cur_buf ^= 1;

@@ -65,8 +65,9 @@ struct StepArgs {
 // Bytes of dynamic LDS the step kernel needs for `block_cells` and `emax`.
 size_t step_lds_bytes(int block_cells, int emax);
 
+// schedule 0: all loads before the first barrier; 1: loads per phase.
 hipError_t launch_step(const StepArgs &a, int block_cells, int threads,
-                       hipStream_t s);
+                       int schedule, hipStream_t s);
 hipError_t launch_clock_set(Clock *c, double t, long long steps,
                             hipStream_t s);
 hipError_t launch_slot_reset(Clock *c, int slot, hipStream_t s);

@@ -205,6 +205,54 @@ __device__ __forceinline__ void boundary_edge(double g, double h_dry,
     cl[2] = -len * (G1 * ny + G2 * nx);
 }
 
+// Update of one cell from the sum R of its three edge contributions:
+// dh = dt R_h / A; the semi-implicit Manning solve for dq (eqs. 33-37);
+// positivity. `clamp` returns the mass added by the positivity fix.
+__device__ __forceinline__ void cell_update(double h_dry, double dt, double A,
+                                            double gm2, double h, double hu,
+                                            double hv, double R0, double R1,
+                                            double R2, double &hn, double &hun,
+                                            double &hvn, double &clamp)
+{
+    const double bh = R0 / A, bx = R1 / A, by = R2 / A;
+    const double dh = dt * bh;
+    const double qn = sqrt(hu * hu + hv * hv);
+    double dqx, dqy;
+    if (h > h_dry && qn > 0.0) {
+        // semi-implicit Manning: S_f = -c|q|q, c = g m^2 h^(-7/3);
+        // (I - dt/2 dS/dq) dq = dt (R_q/A + S_f) + dt/2 (dS/dh) dh
+        const double c = gm2 / (h * h * cbrt(h));
+        const double sfx = -c * qn * hu, sfy = -c * qn * hv;
+        const double jhx = (7.0 / 3.0) * c * qn * hu / h;
+        const double jhy = (7.0 / 3.0) * c * qn * hv / h;
+        const double jxx = -c * (qn + hu * hu / qn);
+        const double jxy = -c * hu * hv / qn;
+        const double jyy = -c * (qn + hv * hv / qn);
+        const double m11 = 1.0 - 0.5 * dt * jxx;
+        const double m12 = -0.5 * dt * jxy;
+        const double m22 = 1.0 - 0.5 * dt * jyy;
+        const double rx = dt * (bx + sfx) + 0.5 * dt * jhx * dh;
+        const double ry = dt * (by + sfy) + 0.5 * dt * jhy * dh;
+        const double det = m11 * m22 - m12 * m12;
+        dqx = (rx * m22 - m12 * ry) / det;
+        dqy = (m11 * ry - m12 * rx) / det;
+    } else {
+        dqx = dt * bx;
+        dqy = dt * by;
+    }
+    hn = h + dh;
+    hun = hu + dqx;
+    hvn = hv + dqy;
+    if (hn < 0.0) {
+        clamp = -A * hn;
+        hn = 0.0;
+    }
+    if (hn <= h_dry) {
+        hun = 0.0;
+        hvn = 0.0;
+    }
+}
+
 __device__ __forceinline__ double wave_min(double v)
 {
 #pragma unroll
@@ -217,6 +265,55 @@ __device__ __forceinline__ double wave_sum(double v)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// End of a step for one block: wave-shuffle then LDS reductions of the
+// block's min R_i/s_i (one 64-bit atomic min into the next clock slot), of
+// the mass added by the positivity fix, and of the non-finite flag; block 0
+// advances the clock.
+template <int NT>
+__device__ __forceinline__ void block_finish(const StepArgs &a, int blk,
+                                             double rs, double clamp,
+                                             unsigned bad, bool unbounded,
+                                             double dt, double tn, int nxt,
+                                             double *red_min, double *red_sum,
+                                             unsigned *red_bad)
+{
+    const int tid = threadIdx.x;
+    rs = wave_min(rs);
+    clamp = wave_sum(clamp);
+    const unsigned long long ballot = __ballot(bad != 0u);
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane == 0) {
+        red_min[wave] = rs;
+        red_sum[wave] = clamp;
+        red_bad[wave] = ballot != 0ull ? 1u : 0u;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double m = red_min[0], cs = red_sum[0];
+        unsigned anybad = red_bad[0];
+        for (int w = 1; w < NT / 64; ++w) {
+            m = fmin(m, red_min[w]);
+            cs += red_sum[w];
+            anybad |= red_bad[w];
+        }
+        if (m < INFINITY)
+            atomicMin(&a.clock->minrs[nxt],
+                      (unsigned long long)__double_as_longlong(m));
+        if (cs != 0.0) a.ledger[blk] += cs;
+        if (anybad || unbounded) {
+            atomicOr(&a.clock->health, (anybad ? 1u : 0u) | (unbounded ? 2u : 0u));
+            atomicMin(&a.clock->bad_step, a.step_index);
+        }
+        if (blk == 0) {
+            const int nn = nxt == 2 ? 0 : nxt + 1;
+            a.clock->t[nxt] = tn;
+            a.clock->last_dt = dt;
+            if (dt > 0.0) a.clock->steps += 1;
+            atomicExch(&a.clock->minrs[nn], kInfBits);
+        }
+    }
 }
 
 // NC cells per block, NT threads (NC or 2 NC): threads below NC own a cell;
@@ -337,44 +434,8 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
         }
         double hn = h, hun = hu, hvn = hv;
         if (dt > 0.0) {
-            const double A = a.area[i];
-            const double bh = R0 / A, bx = R1 / A, by = R2 / A;
-            const double dh = dt * bh;
-            const double qn = sqrt(hu * hu + hv * hv);
-            double dqx, dqy;
-            if (h > h_dry && qn > 0.0) {
-                // semi-implicit Manning: S_f = -c|q|q, c = g m^2 h^(-7/3);
-                // (I - dt/2 dS/dq) dq = dt (R_q/A + S_f) + dt/2 (dS/dh) dh
-                const double c = a.gm2[i] / (h * h * cbrt(h));
-                const double sfx = -c * qn * hu, sfy = -c * qn * hv;
-                const double jhx = (7.0 / 3.0) * c * qn * hu / h;
-                const double jhy = (7.0 / 3.0) * c * qn * hv / h;
-                const double jxx = -c * (qn + hu * hu / qn);
-                const double jxy = -c * hu * hv / qn;
-                const double jyy = -c * (qn + hv * hv / qn);
-                const double m11 = 1.0 - 0.5 * dt * jxx;
-                const double m12 = -0.5 * dt * jxy;
-                const double m22 = 1.0 - 0.5 * dt * jyy;
-                const double rx = dt * (bx + sfx) + 0.5 * dt * jhx * dh;
-                const double ry = dt * (by + sfy) + 0.5 * dt * jhy * dh;
-                const double det = m11 * m22 - m12 * m12;
-                dqx = (rx * m22 - m12 * ry) / det;
-                dqy = (m11 * ry - m12 * rx) / det;
-            } else {
-                dqx = dt * bx;
-                dqy = dt * by;
-            }
-            hn = h + dh;
-            hun = hu + dqx;
-            hvn = hv + dqy;
-            if (hn < 0.0) {
-                clamp = -A * hn;
-                hn = 0.0;
-            }
-            if (hn <= h_dry) {
-                hun = 0.0;
-                hvn = 0.0;
-            }
+            cell_update(h_dry, dt, a.area[i], a.gm2[i], h, hu, hv, R0, R1, R2,
+                        hn, hun, hvn, clamp);
         }
         a.h1[i] = hn;
         a.hu1[i] = hun;
@@ -386,41 +447,209 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
         }
     }
 
-    // block reductions: min R/s, sum of clamped mass, any non-finite value
-    rs = wave_min(rs);
-    clamp = wave_sum(clamp);
-    const unsigned long long ballot = __ballot(bad != 0u);
-    const int wave = tid >> 6, lane = tid & 63;
-    if (lane == 0) {
-        red_min[wave] = rs;
-        red_sum[wave] = clamp;
-        red_bad[wave] = ballot != 0ull ? 1u : 0u;
+    block_finish<NT>(a, blk, rs, clamp, bad, unbounded, dt, tn, nxt, red_min,
+                     red_sum, red_bad);
+}
+
+// Same step with every independent load issued before the first barrier:
+// the owned cell's state and per-cell data, the thread's edge record, and then
+// (depending only on that record) the state of a neighbour in another block.
+// A block then waits for two memory round trips instead of four.
+template <int NC, int NT>
+__global__ __launch_bounds__(NT) void swe_step_kernel_pf(StepArgs a)
+{
+    extern __shared__ double lds[];
+    __shared__ double red_min[NT / 64];
+    __shared__ double red_sum[NT / 64];
+    __shared__ unsigned red_bad[NT / 64];
+    double *s_h = lds;
+    double *s_u = s_h + NC;
+    double *s_v = s_u + NC;
+    double *s_z = s_v + NC;
+    double *s_c = s_z + NC;   // 6 x emax: left contributions, then right
+    const int emax = a.emax;
+
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int c0 = a.blk_cell[blk];
+    const int nc = a.blk_cell[blk + 1] - c0;
+    const int e0 = a.blk_edge[blk];
+    const int ne = a.blk_edge[blk + 1] - e0;
+    const int tid = threadIdx.x;
+    const double g = a.g, h_dry = a.h_dry;
+
+    // loads, all issued up front
+    const bool own = tid < NC && tid < nc;
+    const int i = c0 + tid;
+    double h = 0.0, hu = 0.0, hv = 0.0, zc = 0.0;
+    double A = 1.0, gm2 = 0.0, inr = 0.0;
+    unsigned long long pk = 0;
+    if (own) {
+        h = a.h0[i];
+        hu = a.hu0[i];
+        hv = a.hv0[i];
+        zc = a.z[i];
+        pk = a.slots[i];
+        A = a.area[i];
+        gm2 = a.gm2[i];
+        inr = a.inradius[i];
+    }
+    const bool has_edge = tid < ne;
+    int l = 0, r = 0;
+    double nx = 0.0, ny = 0.0, len = 0.0;
+    if (has_edge) {
+        l = a.be_left[e0 + tid];
+        r = a.be_right[e0 + tid];
+        nx = a.be_nx[e0 + tid];
+        ny = a.be_ny[e0 + tid];
+        len = a.be_len[e0 + tid];
+    }
+    const bool l_in = unsigned(l - c0) < unsigned(nc);
+    const bool r_in = r >= 0 && unsigned(r - c0) < unsigned(nc);
+    // the one side (if any) that lies in another block
+    CellState X;
+    X.h = 0.0; X.u = 0.0; X.v = 0.0; X.z = 0.0;
+    double xhu = 0.0, xhv = 0.0;
+    const bool need_x = has_edge && (!l_in || (r >= 0 && !r_in));
+    if (need_x) {
+        const int x = l_in ? r : l;
+        X.h = a.h0[x];
+        xhu = a.hu0[x];
+        xhv = a.hv0[x];
+        X.z = a.z[x];
+    }
+
+    // time step of this step: CFL * min R/s of U^n, bounded, clipped to t_end
+    const int cur = a.cur;
+    const int nxt = cur == 2 ? 0 : cur + 1;
+    const double mrs = __longlong_as_double((long long)a.clock->minrs[cur]);
+    const double t = a.clock->t[cur];
+    double dt = fmin(a.cfl * mrs, a.dt_max);
+    const double rem = a.t_end - t;
+    double tn;
+    if (dt >= rem) {
+        dt = rem > 0.0 ? rem : 0.0;
+        tn = rem > 0.0 ? a.t_end : t;
+    } else {
+        tn = t + dt;
+    }
+    const bool unbounded = !(dt < INFINITY);
+    if (unbounded) {
+        dt = 0.0;
+        tn = t;
+    }
+
+    // stage this block's cells
+    if (own) {
+        s_h[tid] = h;
+        s_z[tid] = zc;
+        if (h > h_dry) {
+            s_u[tid] = hu / h;
+            s_v[tid] = hv / h;
+        } else {
+            s_u[tid] = 0.0;
+            s_v[tid] = 0.0;
+        }
+    }
+    if (need_x && X.h > h_dry) {
+        X.u = xhu / X.h;
+        X.v = xhv / X.h;
     }
     __syncthreads();
-    if (tid == 0) {
-        double m = red_min[0], cs = red_sum[0];
-        unsigned anybad = red_bad[0];
-        for (int w = 1; w < NT / 64; ++w) {
-            m = fmin(m, red_min[w]);
-            cs += red_sum[w];
-            anybad |= red_bad[w];
+
+    // every edge of the block once
+    if (has_edge) {
+        CellState L, R;
+        if (l_in) {
+            const int ll = l - c0;
+            L.h = s_h[ll]; L.u = s_u[ll]; L.v = s_v[ll]; L.z = s_z[ll];
+        } else {
+            L = X;
         }
-        if (m < INFINITY)
-            atomicMin(&a.clock->minrs[nxt],
-                      (unsigned long long)__double_as_longlong(m));
-        if (cs != 0.0) a.ledger[blk] += cs;
-        if (anybad || unbounded) {
-            atomicOr(&a.clock->health, (anybad ? 1u : 0u) | (unbounded ? 2u : 0u));
-            atomicMin(&a.clock->bad_step, a.step_index);
+        double cl[3], cr[3];
+        if (r >= 0) {
+            if (r_in) {
+                const int rr = r - c0;
+                R.h = s_h[rr]; R.u = s_u[rr]; R.v = s_v[rr]; R.z = s_z[rr];
+            } else {
+                R = X;
+            }
+            interior_edge(g, h_dry, L, R, nx, ny, len, cl, cr);
+        } else {
+            const BcEntry bc = a.bc[-1 - r];
+            boundary_edge(g, h_dry, bc, L, nx, ny, len, cl);
+            cr[0] = 0.0; cr[1] = 0.0; cr[2] = 0.0;
         }
-        if (blk == 0) {
-            const int nn = nxt == 2 ? 0 : nxt + 1;
-            a.clock->t[nxt] = tn;
-            a.clock->last_dt = dt;
-            if (dt > 0.0) a.clock->steps += 1;
-            atomicExch(&a.clock->minrs[nn], kInfBits);
+        s_c[tid] = cl[0];
+        s_c[emax + tid] = cl[1];
+        s_c[2 * emax + tid] = cl[2];
+        s_c[3 * emax + tid] = cr[0];
+        s_c[4 * emax + tid] = cr[1];
+        s_c[5 * emax + tid] = cr[2];
+    }
+    for (int k = tid + NT; k < ne; k += NT) {   // blocks with > NT edges
+        const int l2 = a.be_left[e0 + k];
+        const int r2 = a.be_right[e0 + k];
+        CellState L, R;
+        if (unsigned(l2 - c0) < unsigned(nc)) {
+            const int ll = l2 - c0;
+            L.h = s_h[ll]; L.u = s_u[ll]; L.v = s_v[ll]; L.z = s_z[ll];
+        } else {
+            L = load_cell(a, l2);
+        }
+        double cl[3], cr[3];
+        if (r2 >= 0) {
+            if (unsigned(r2 - c0) < unsigned(nc)) {
+                const int rr = r2 - c0;
+                R.h = s_h[rr]; R.u = s_u[rr]; R.v = s_v[rr]; R.z = s_z[rr];
+            } else {
+                R = load_cell(a, r2);
+            }
+            interior_edge(g, h_dry, L, R, a.be_nx[e0 + k], a.be_ny[e0 + k],
+                          a.be_len[e0 + k], cl, cr);
+        } else {
+            const BcEntry bc = a.bc[-1 - r2];
+            boundary_edge(g, h_dry, bc, L, a.be_nx[e0 + k], a.be_ny[e0 + k],
+                          a.be_len[e0 + k], cl);
+            cr[0] = 0.0; cr[1] = 0.0; cr[2] = 0.0;
+        }
+        s_c[k] = cl[0];
+        s_c[emax + k] = cl[1];
+        s_c[2 * emax + k] = cl[2];
+        s_c[3 * emax + k] = cr[0];
+        s_c[4 * emax + k] = cr[1];
+        s_c[5 * emax + k] = cr[2];
+    }
+    __syncthreads();
+
+    // cell update
+    double rs = INFINITY, clamp = 0.0;
+    unsigned bad = 0;
+    if (own) {
+        double R0 = 0.0, R1 = 0.0, R2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const unsigned s = unsigned(pk >> (16 * k)) & 0xffffu;
+            const double *src = s_c + (s >> 15) * 3 * emax + (s & 0x7fffu);
+            R0 += src[0];
+            R1 += src[emax];
+            R2 += src[2 * emax];
+        }
+        double hn = h, hun = hu, hvn = hv;
+        if (dt > 0.0) {
+            cell_update(h_dry, dt, A, gm2, h, hu, hv, R0, R1, R2, hn, hun, hvn,
+                        clamp);
+        }
+        a.h1[i] = hn;
+        a.hu1[i] = hun;
+        a.hv1[i] = hvn;
+        if (!isfinite(hn) || !isfinite(hun) || !isfinite(hvn)) bad = 1u;
+        if (hn > h_dry) {
+            const double u = hun / hn, v = hvn / hn;
+            rs = inr / (sqrt(g * hn) + sqrt(u * u + v * v));
         }
     }
+    block_finish<NT>(a, blk, rs, clamp, bad, unbounded, dt, tn, nxt,
+                     red_min, red_sum, red_bad);
 }
 
 __global__ void clock_set_kernel(Clock *c, double t, long long steps)
@@ -601,34 +830,39 @@ size_t step_lds_bytes(int block_cells, int emax)
 
 namespace {
 template <int NC, int NT>
-void launch_one(const StepArgs &a, size_t lds, hipStream_t s)
+void launch_one(const StepArgs &a, size_t lds, int schedule, hipStream_t s)
 {
-    hipLaunchKernelGGL((swe_step_kernel<NC, NT>), dim3(a.n_blocks), dim3(NT),
-                       lds, s, a);
+    if (schedule == 0)
+        hipLaunchKernelGGL((swe_step_kernel_pf<NC, NT>), dim3(a.n_blocks),
+                           dim3(NT), lds, s, a);
+    else
+        hipLaunchKernelGGL((swe_step_kernel<NC, NT>), dim3(a.n_blocks),
+                           dim3(NT), lds, s, a);
 }
 }  // namespace
 
 hipError_t launch_step(const StepArgs &a, int block_cells, int threads,
-                       hipStream_t s)
+                       int schedule, hipStream_t s)
 {
     const size_t lds = step_lds_bytes(block_cells, a.emax);
     const bool twice = threads == 2 * block_cells;
     if (!twice && threads != block_cells) return hipErrorInvalidValue;
     switch (block_cells) {
     case 64:
-        twice ? launch_one<64, 128>(a, lds, s) : launch_one<64, 64>(a, lds, s);
+        twice ? launch_one<64, 128>(a, lds, schedule, s)
+              : launch_one<64, 64>(a, lds, schedule, s);
         break;
     case 128:
-        twice ? launch_one<128, 256>(a, lds, s)
-              : launch_one<128, 128>(a, lds, s);
+        twice ? launch_one<128, 256>(a, lds, schedule, s)
+              : launch_one<128, 128>(a, lds, schedule, s);
         break;
     case 256:
-        twice ? launch_one<256, 512>(a, lds, s)
-              : launch_one<256, 256>(a, lds, s);
+        twice ? launch_one<256, 512>(a, lds, schedule, s)
+              : launch_one<256, 256>(a, lds, schedule, s);
         break;
     case 512:
-        twice ? launch_one<512, 1024>(a, lds, s)
-              : launch_one<512, 512>(a, lds, s);
+        twice ? launch_one<512, 1024>(a, lds, schedule, s)
+              : launch_one<512, 512>(a, lds, schedule, s);
         break;
     default:
         return hipErrorInvalidValue;

@@ -45,7 +45,8 @@ class swe_params(C.Structure):
     _fields_ = [("g", C.c_double), ("cfl", C.c_double), ("h_dry", C.c_double),
                 ("dt_max", C.c_double), ("check_every", C.c_int32),
                 ("block_cells", C.c_int32), ("reorder", C.c_int32),
-                ("block_threads", C.c_int32)]
+                ("block_threads", C.c_int32), ("load_schedule", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class swe_mesh_stats(C.Structure):

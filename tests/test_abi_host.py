@@ -155,7 +155,9 @@ def test_bad_fields_are_rejected_on_the_host(ctx, field, value, status):
                                         ("h_dry", -1e-3), ("dt_max", 0.0),
                                         ("check_every", 0),
                                         ("block_cells", 100),
-                                        ("reorder", 2), ("block_threads", 100)])
+                                        ("reorder", 2), ("block_threads", 100),
+                                        ("load_schedule", 2),
+                                        ("reserved", 1)])
 def test_bad_params_are_rejected(ctx, name, value):
     p = S.swe_default_params()
     setattr(p, name, value)

@@ -96,11 +96,12 @@ def test_lake_at_rest_gpu():
     assert np.max(np.abs(h[wet] + case.z[wet] - 0.12)) <= 1e-12
 
 
-@pytest.mark.parametrize("block_cells,reorder,threads", [
-    (64, True, 0), (128, True, 0), (512, True, 0), (256, False, 0),
-    (256, True, 256), (64, True, 64), (512, True, 512)])
+@pytest.mark.parametrize("block_cells,reorder,threads,schedule", [
+    (64, True, 0, 0), (128, True, 0, 0), (512, True, 0, 0),
+    (256, False, 0, 0), (256, True, 256, 0), (64, True, 64, 0),
+    (512, True, 512, 0), (256, True, 0, 1), (128, True, 128, 1)])
 def test_blocking_and_order_do_not_change_bits(block_cells, reorder,
-                                               threads):
+                                               threads, schedule):
     """Per-cell arithmetic is independent of how cells are grouped into
     blocks, ordered and spread over threads: results are bitwise those of
     the default layout."""
@@ -109,7 +110,7 @@ def test_blocking_and_order_do_not_change_bits(block_cells, reorder,
     ref.advance(60)
     a = ref.state()
     s = solver(case, block_cells=block_cells, reorder=reorder,
-               params={"block_threads": threads})
+               params={"block_threads": threads, "load_schedule": schedule})
     s.advance(60)
     b = s.state()
     for x, y in zip(a, b):
