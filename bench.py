@@ -180,7 +180,7 @@ def main():
     ap.add_argument("--cells", type=int, default=13_000_000)
     ap.add_argument("--block-cells", type=int, default=256)
     ap.add_argument("--block-threads", type=int, default=0,
-                    help="0: automatic (2 x block cells)")
+                    help="0: automatic (= block cells)")
     ap.add_argument("--workers", type=int,
                     default=min(16, os.cpu_count() or 1))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -295,8 +295,8 @@ def main():
         dtype="f64", data="synthetic",
         config=dict(workload=desc, n_cells=n, n_edges=info["n_edges"],
                     block_cells=info["block_cells"],
-                    block_threads=args.block_threads or
-                    2 * info["block_cells"], setup_s=round(setup_s, 2),
+                    block_threads=args.block_threads or info["block_cells"],
+                    setup_s=round(setup_s, 2),
                     effective_gbs=achieved),
         roofline=roofline, cpu_baseline=base)
     print(json.dumps(out), flush=True)

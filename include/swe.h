@@ -79,11 +79,11 @@ typedef struct {
     int32_t reorder;       /* 1: space-filling-curve cell order (default);
                               0: keep the user order; next set_mesh           */
     int32_t block_threads; /* threads per block: block_cells, 2*block_cells,
-                              or 0 = automatic (2*block_cells, so that the
-                              block's edges take one pass) (0)                */
-    int32_t load_schedule; /* 0: issue every load of a block before its first
-                              barrier (default); 1: load per phase. Same
-                              results bit for bit; a tuning switch           */
+                              or 0 = automatic (= block_cells) (0)            */
+    int32_t load_schedule; /* 0: loads per phase, skipping inputs that cannot
+                              change the result on dry cells (default);
+                              1: every load issued before the first barrier.
+                              Same results; a tuning switch                   */
     int32_t reserved;      /* must be 0                                       */
 } swe_params;
 

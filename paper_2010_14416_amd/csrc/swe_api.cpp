@@ -697,7 +697,7 @@ swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
     a.n_blocks = m.n_blocks;
     a.emax = m.max_block_edges;
     const int threads = c->params.block_threads == 0
-                            ? 2 * m.block_cells
+                            ? m.block_cells
                             : c->params.block_threads;
     auto launch_n = [&](int64_t n) -> swe_status {
         for (int64_t k = 0; k < n; ++k) {

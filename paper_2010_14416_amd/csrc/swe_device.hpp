@@ -65,7 +65,8 @@ struct StepArgs {
 // Bytes of dynamic LDS the step kernel needs for `block_cells` and `emax`.
 size_t step_lds_bytes(int block_cells, int emax);
 
-// schedule 0: all loads before the first barrier; 1: loads per phase.
+// schedule 0: loads per phase, skipping inputs that cannot change the
+// result on dry cells; 1: every load issued before the first barrier.
 hipError_t launch_step(const StepArgs &a, int block_cells, int threads,
                        int schedule, hipStream_t s);
 hipError_t launch_clock_set(Clock *c, double t, long long steps,

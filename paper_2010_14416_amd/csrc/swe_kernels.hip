@@ -209,10 +209,11 @@ __device__ __forceinline__ void boundary_edge(double g, double h_dry,
 // dh = dt R_h / A; the semi-implicit Manning solve for dq (eqs. 33-37);
 // positivity. `clamp` returns the mass added by the positivity fix.
 __device__ __forceinline__ void cell_update(double h_dry, double dt, double A,
-                                            double gm2, double h, double hu,
-                                            double hv, double R0, double R1,
-                                            double R2, double &hn, double &hun,
-                                            double &hvn, double &clamp)
+                                            const double *gm2, double h,
+                                            double hu, double hv, double R0,
+                                            double R1, double R2, double &hn,
+                                            double &hun, double &hvn,
+                                            double &clamp)
 {
     const double bh = R0 / A, bx = R1 / A, by = R2 / A;
     const double dh = dt * bh;
@@ -221,7 +222,7 @@ __device__ __forceinline__ void cell_update(double h_dry, double dt, double A,
     if (h > h_dry && qn > 0.0) {
         // semi-implicit Manning: S_f = -c|q|q, c = g m^2 h^(-7/3);
         // (I - dt/2 dS/dq) dq = dt (R_q/A + S_f) + dt/2 (dS/dh) dh
-        const double c = gm2 / (h * h * cbrt(h));
+        const double c = *gm2 / (h * h * cbrt(h));
         const double sfx = -c * qn * hu, sfy = -c * qn * hv;
         const double jhx = (7.0 / 3.0) * c * qn * hu / h;
         const double jhy = (7.0 / 3.0) * c * qn * hv / h;
@@ -317,7 +318,13 @@ __device__ __forceinline__ void block_finish(const StepArgs &a, int blk,
 }
 
 // NC cells per block, NT threads (NC or 2 NC): threads below NC own a cell;
-// all NT threads share the block's edges.
+// all NT threads share the block's edges. Loads follow the phases and skip
+// inputs that cannot change the result: the geometry of an interior edge
+// whose two cells hold no water at all (h == 0: its flux and bed-slope terms
+// are zero), or of a wall / transmissive edge of such a cell, and the area of
+// a cell at or below h_dry whose three edges bring exactly nothing (then
+// R/A = R). The friction coefficient and inscribed radius are read only by
+// wet cells.
 template <int NC, int NT>
 __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
 {
@@ -384,30 +391,36 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
     for (int k = tid; k < ne; k += NT) {
         const int l = a.be_left[e0 + k];
         const int r = a.be_right[e0 + k];
-        const double nx = a.be_nx[e0 + k];
-        const double ny = a.be_ny[e0 + k];
-        const double len = a.be_len[e0 + k];
-        CellState L;
+        CellState L, R;
         const unsigned ll = unsigned(l - c0);
         if (ll < unsigned(nc)) {
             L.h = s_h[ll]; L.u = s_u[ll]; L.v = s_v[ll]; L.z = s_z[ll];
         } else {
             L = load_cell(a, l);
         }
-        double cl[3], cr[3];
+        BcEntry bc{};
+        bool idle;
         if (r >= 0) {
-            CellState R;
             const unsigned rr = unsigned(r - c0);
             if (rr < unsigned(nc)) {
                 R.h = s_h[rr]; R.u = s_u[rr]; R.v = s_v[rr]; R.z = s_z[rr];
             } else {
                 R = load_cell(a, r);
             }
-            interior_edge(g, h_dry, L, R, nx, ny, len, cl, cr);
+            idle = L.h == 0.0 && R.h == 0.0;
         } else {
-            const BcEntry bc = a.bc[-1 - r];
-            boundary_edge(g, h_dry, bc, L, nx, ny, len, cl);
-            cr[0] = 0.0; cr[1] = 0.0; cr[2] = 0.0;
+            bc = a.bc[-1 - r];
+            idle = L.h == 0.0 && (bc.kind == 0 || bc.kind == 1);
+        }
+        double cl[3] = {0.0, 0.0, 0.0}, cr[3] = {0.0, 0.0, 0.0};
+        if (!idle) {
+            const double nx = a.be_nx[e0 + k];
+            const double ny = a.be_ny[e0 + k];
+            const double len = a.be_len[e0 + k];
+            if (r >= 0)
+                interior_edge(g, h_dry, L, R, nx, ny, len, cl, cr);
+            else
+                boundary_edge(g, h_dry, bc, L, nx, ny, len, cl);
         }
         s_c[k] = cl[0];
         s_c[emax + k] = cl[1];
@@ -434,8 +447,16 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
         }
         double hn = h, hun = hu, hvn = hv;
         if (dt > 0.0) {
-            cell_update(h_dry, dt, a.area[i], a.gm2[i], h, hu, hv, R0, R1, R2,
-                        hn, hun, hvn, clamp);
+            if (h <= h_dry && R0 == 0.0 && R1 == 0.0 && R2 == 0.0) {
+                // R/A = R exactly; no friction below h_dry; h + dt*(+-0)
+                // cannot go negative
+                hn = h + dt * R0;
+                hun = 0.0;
+                hvn = 0.0;
+            } else {
+                cell_update(h_dry, dt, a.area[i], a.gm2 + i, h, hu, hv, R0,
+                            R1, R2, hn, hun, hvn, clamp);
+            }
         }
         a.h1[i] = hn;
         a.hu1[i] = hun;
@@ -446,9 +467,8 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
             rs = a.inradius[i] / (sqrt(g * hn) + sqrt(u * u + v * v));
         }
     }
-
-    block_finish<NT>(a, blk, rs, clamp, bad, unbounded, dt, tn, nxt, red_min,
-                     red_sum, red_bad);
+    block_finish<NT>(a, blk, rs, clamp, bad, unbounded, dt, tn, nxt,
+                     red_min, red_sum, red_bad);
 }
 
 // Same step with every independent load issued before the first barrier:
@@ -636,8 +656,8 @@ __global__ __launch_bounds__(NT) void swe_step_kernel_pf(StepArgs a)
         }
         double hn = h, hun = hu, hvn = hv;
         if (dt > 0.0) {
-            cell_update(h_dry, dt, A, gm2, h, hu, hv, R0, R1, R2, hn, hun, hvn,
-                        clamp);
+            cell_update(h_dry, dt, A, &gm2, h, hu, hv, R0, R1, R2, hn, hun,
+                        hvn, clamp);
         }
         a.h1[i] = hn;
         a.hu1[i] = hun;
@@ -833,10 +853,10 @@ template <int NC, int NT>
 void launch_one(const StepArgs &a, size_t lds, int schedule, hipStream_t s)
 {
     if (schedule == 0)
-        hipLaunchKernelGGL((swe_step_kernel_pf<NC, NT>), dim3(a.n_blocks),
+        hipLaunchKernelGGL((swe_step_kernel<NC, NT>), dim3(a.n_blocks),
                            dim3(NT), lds, s, a);
     else
-        hipLaunchKernelGGL((swe_step_kernel<NC, NT>), dim3(a.n_blocks),
+        hipLaunchKernelGGL((swe_step_kernel_pf<NC, NT>), dim3(a.n_blocks),
                            dim3(NT), lds, s, a);
 }
 }  // namespace
