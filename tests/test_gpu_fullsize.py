@@ -87,9 +87,7 @@ def test_bumps_1M_one_step_and_full_run(bumps):
 @pytest.fixture(scope="module")
 def river():
     t0 = time.time()
-    # one process: earlier tests have initialised the GPU in this process,
-    # so no worker processes are forked from it
-    case = W.river(workers=1)
+    case = W.river(workers=min(16, os.cpu_count() or 1))   # threads
     say(f"[fullsize] river {case.n_cells} cells generated in "
         f"{time.time() - t0:.1f} s")
     s = solver(case)

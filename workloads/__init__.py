@@ -338,11 +338,13 @@ def river(n_target: int = 13_000_000, seed: int = 3, n_strips: int = 16,
         strips.append((side, inner))
 
     if workers > 1:
-        import multiprocessing as mp
-        ctx = mp.get_context("fork")
-        with ctx.Pool(min(workers, n_strips)) as pool:
-            simp = pool.map(_triangulate_strip,
-                            [np.concatenate(st) for st in strips])
+        # threads, not processes: Qhull releases the GIL, and no process is
+        # forked (a forked child of a profiled or GPU-initialised process can
+        # hang on exit)
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(min(workers, n_strips)) as ex:
+            simp = list(ex.map(_triangulate_strip,
+                               [np.concatenate(st) for st in strips]))
     else:
         simp = [_triangulate_strip(np.concatenate(st)) for st in strips]
 
