@@ -24,11 +24,10 @@ namespace {
 // Device buffers, carved from one workspace (256-byte aligned pieces).
 struct DevBufs {
     double *h[2], *hu[2], *hv[2];
-    double *z, *man, *gm2, *inv_area, *area, *inr;
-    uint64_t *slots;
+    double *z, *man, *gm2, *area, *inr;
     int32_t *internal_of_user, *user_of_internal;
     int32_t *blk_cell, *blk_edge;
-    int32_t *be_left, *be_right;
+    int32_t *be_a, *be_b;
     double *be_nx, *be_ny, *be_len;
     BcEntry *bc;
     Clock *clock;
@@ -107,7 +106,7 @@ size_t layout(const BlockMesh &m, char *base, DevBufs *d)
         return p;
     };
     const size_t nc = size_t(m.n_cells), nb = size_t(m.n_blocks);
-    const size_t nbe = m.be_left.size();
+    const size_t nbe = m.be_a.size();
     DevBufs t{};
     for (int k = 0; k < 2; ++k) {
         t.h[k] = (double *)take(nc * 8);
@@ -117,16 +116,14 @@ size_t layout(const BlockMesh &m, char *base, DevBufs *d)
     t.z = (double *)take(nc * 8);
     t.man = (double *)take(nc * 8);
     t.gm2 = (double *)take(nc * 8);
-    t.inv_area = (double *)take(nc * 8);
     t.area = (double *)take(nc * 8);
     t.inr = (double *)take(nc * 8);
-    t.slots = (uint64_t *)take(nc * 8);
     t.internal_of_user = (int32_t *)take(nc * 4);
     t.user_of_internal = (int32_t *)take(nc * 4);
     t.blk_cell = (int32_t *)take((nb + 1) * 4);
     t.blk_edge = (int32_t *)take((nb + 1) * 4);
-    t.be_left = (int32_t *)take(nbe * 4);
-    t.be_right = (int32_t *)take(nbe * 4);
+    t.be_a = (int32_t *)take(nbe * 4);
+    t.be_b = (int32_t *)take(nbe * 4);
     t.be_nx = (double *)take(nbe * 8);
     t.be_ny = (double *)take(nbe * 8);
     t.be_len = (double *)take(nbe * 8);
@@ -187,11 +184,8 @@ swe_status prepare(swe_ctx *c)
         }
         layout(m, (char *)c->ws, &c->d);
         DevBufs &d = c->d;
-        if ((st = upload(c, d.inv_area, m.inv_area.data(), nc))) return st;
         if ((st = upload(c, d.area, m.area.data(), nc))) return st;
         if ((st = upload(c, d.inr, m.inradius.data(), nc))) return st;
-        if ((st = upload(c, d.slots, (const uint64_t *)m.slots.data(), nc)))
-            return st;
         if ((st = upload(c, d.internal_of_user, m.internal_of_user.data(), nc)))
             return st;
         if ((st = upload(c, d.user_of_internal, m.user_of_internal.data(), nc)))
@@ -200,9 +194,9 @@ swe_status prepare(swe_ctx *c)
             return st;
         if ((st = upload(c, d.blk_edge, m.blk_edge.data(), m.blk_edge.size())))
             return st;
-        const size_t nbe = m.be_left.size();
-        if ((st = upload(c, d.be_left, m.be_left.data(), nbe))) return st;
-        if ((st = upload(c, d.be_right, m.be_right.data(), nbe))) return st;
+        const size_t nbe = m.be_a.size();
+        if ((st = upload(c, d.be_a, m.be_a.data(), nbe))) return st;
+        if ((st = upload(c, d.be_b, m.be_b.data(), nbe))) return st;
         if ((st = upload(c, d.be_nx, m.be_nx.data(), nbe))) return st;
         if ((st = upload(c, d.be_ny, m.be_ny.data(), nbe))) return st;
         if ((st = upload(c, d.be_len, m.be_len.data(), nbe))) return st;
@@ -497,7 +491,7 @@ swe_status swe_mesh_info(const swe_ctx *c, swe_mesh_stats *o)
     o->n_edges = m.n_edges;
     o->n_boundary_edges = m.n_bnd_edges;
     o->n_blocks = m.n_blocks;
-    o->n_block_edges = int64_t(m.be_left.size());
+    o->n_block_edges = int64_t(m.be_a.size());
     o->block_cells = m.block_cells;
     o->max_block_edges = m.max_block_edges;
     o->min_inradius = m.min_inradius;
@@ -675,15 +669,13 @@ swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
     swe::StepArgs a{};
     a.blk_cell = c->d.blk_cell;
     a.blk_edge = c->d.blk_edge;
-    a.be_left = c->d.be_left;
-    a.be_right = c->d.be_right;
+    a.be_a = c->d.be_a;
+    a.be_b = c->d.be_b;
     a.be_nx = c->d.be_nx;
     a.be_ny = c->d.be_ny;
     a.be_len = c->d.be_len;
-    a.slots = c->d.slots;
     a.z = c->d.z;
     a.gm2 = c->d.gm2;
-    a.inv_area = c->d.inv_area;
     a.area = c->d.area;
     a.inradius = c->d.inr;
     a.bc = c->d.bc;
@@ -695,7 +687,6 @@ swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
     a.dt_max = c->params.dt_max;
     a.t_end = t_end;
     a.n_blocks = m.n_blocks;
-    a.emax = m.max_block_edges;
     const int threads = c->params.block_threads == 0
                             ? m.block_cells
                             : c->params.block_threads;

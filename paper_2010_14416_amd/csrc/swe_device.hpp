@@ -17,31 +17,36 @@ struct BcEntry {
     double q;       // inflow discharge per unit length, Q / tag length
 };
 
+// Lanes of the time-step minimum: blocks combine their minimum into lane
+// (workgroup id mod 8), which follows the round-robin dispatch over the 8
+// XCDs; each lane has its own 128-byte line.
+constexpr int kClockLanes = 8;
+
 // Device-resident clock. Step n reads slot n % 3 and writes slot (n+1) % 3;
 // slot (n+2) % 3 is reset by step n for use by step n+1.
 struct Clock {
     double t[3];                   // simulated time at the start of a step
-    unsigned long long minrs[3];   // bits of min over wet cells R_i / s_i
     double last_dt;
     long long steps;               // steps with dt > 0
     unsigned int health;           // bit 0: non-finite state, bit 1: dt = inf
     unsigned int pad;
     long long bad_step;            // first step index that raised health
+    long long pad2[9];
+    // bits of min over wet cells of R_i / s_i, per slot and lane
+    unsigned long long minrs[3][kClockLanes][16];
 };
 
 struct StepArgs {
     // mesh (internal order)
     const int32_t *blk_cell;
     const int32_t *blk_edge;
-    const int32_t *be_left;
-    const int32_t *be_right;
+    const int32_t *be_a;      // left side of each block edge (coded)
+    const int32_t *be_b;      // right side (coded)
     const double *be_nx;
     const double *be_ny;
     const double *be_len;
-    const uint64_t *slots;
     const double *z;
     const double *gm2;        // g m^2 per cell
-    const double *inv_area;
     const double *area;
     const double *inradius;
     const BcEntry *bc;
@@ -56,17 +61,15 @@ struct StepArgs {
     double *ledger;           // per block: mass added by the positivity fix
     double g, cfl, h_dry, dt_max, t_end;
     int32_t n_blocks;
-    int32_t emax;             // stride of the per-block edge results in LDS
     int32_t cur;              // clock slot of this step
-    int32_t pad;
     long long step_index;
 };
 
-// Bytes of dynamic LDS the step kernel needs for `block_cells` and `emax`.
-size_t step_lds_bytes(int block_cells, int emax);
+// Bytes of dynamic LDS the step kernel needs per block.
+size_t step_lds_bytes(int block_cells);
 
-// schedule 0: loads per phase, skipping inputs that cannot change the
-// result on dry cells; 1: every load issued before the first barrier.
+// schedule 0: edge geometry read only where the edge can carry a flux;
+// 1: edge geometry read with the edge record, before the first barrier.
 hipError_t launch_step(const StepArgs &a, int block_cells, int threads,
                        int schedule, hipStream_t s);
 hipError_t launch_clock_set(Clock *c, double t, long long steps,

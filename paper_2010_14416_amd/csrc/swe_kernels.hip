@@ -33,6 +33,7 @@
 #include <cmath>
 
 #include "swe_device.hpp"
+#include "swe_mesh.hpp"
 
 namespace swe {
 namespace {
@@ -133,87 +134,102 @@ __device__ __forceinline__ CellState load_cell(const StepArgs &a, int c)
     return s;
 }
 
-// Contributions of one interior edge (left cell L, right cell R, unit normal
-// n from L to R, length len) to both cells' right-hand sides:
+// Contributions of one edge to its cells' right-hand sides, with F the
+// back-rotated flux in the frame of the unit normal n (left to right,
+// outward on the boundary) and len the edge length:
+// interior edge (left cell L, right cell R): HLLC of the reconstructed
+// states (eq. 28; reconstructed depths at or below h_dry count as zero) and
+// the bed-slope terms (eq. 30),
 //   cl = -len F + len (g/2)(hL**^2 - hL^2)(0, n),
-//   cr = +len F - len (g/2)(hR**^2 - hR^2)(0, n),
-// with F the back-rotated HLLC flux of the reconstructed states (eq. 28);
-// reconstructed depths at or below h_dry count as zero.
-__device__ __forceinline__ void interior_edge(double g, double h_dry,
-                                              const CellState &L,
-                                              const CellState &R, double nx,
-                                              double ny, double len,
-                                              double cl[3], double cr[3])
+//   cr = +len F - len (g/2)(hR**^2 - hR^2)(0, n);
+// boundary edge of cell L: wall, transmissive, inflow of discharge q per
+// unit length, or a ghost state of fixed depth / fixed surface elevation
+// with the cell's velocity through HLLC, cl = -len F (cr unused).
+// One Riemann solve serves every kind.
+__device__ __forceinline__ void edge_contrib(double g, double h_dry, bool bnd,
+                                             const BcEntry &bc,
+                                             const CellState &L,
+                                             const CellState &R, double nx,
+                                             double ny, double len,
+                                             double &cl0, double &cl1,
+                                             double &cl2, double &cr0,
+                                             double &cr1, double &cr2)
 {
-    const double zs = fmax(L.z, R.z);
-    double hl = L.h - (zs - L.z);
-    double hr = R.h - (zs - R.z);
-    if (hl <= h_dry) hl = 0.0;
-    if (hr <= h_dry) hr = 0.0;
-    double G0, G1, G2;
-    hllc(g, h_dry, hl, L.u * nx + L.v * ny, -L.u * ny + L.v * nx, hr,
-         R.u * nx + R.v * ny, -R.u * ny + R.v * nx, G0, G1, G2);
+    const double unl = L.u * nx + L.v * ny, utl = -L.u * ny + L.v * nx;
+    double hl, hr, unr, utr;
+    double G0 = 0.0, G1 = 0.0, G2 = 0.0;
+    bool solve = true;
+    if (!bnd) {
+        const double zs = fmax(L.z, R.z);
+        hl = L.h - (zs - L.z);
+        hr = R.h - (zs - R.z);
+        if (hl <= h_dry) hl = 0.0;
+        if (hr <= h_dry) hr = 0.0;
+        unr = R.u * nx + R.v * ny;
+        utr = -R.u * ny + R.v * nx;
+    } else {
+        hl = L.h;
+        unr = unl;
+        utr = utl;
+        hr = 0.0;
+        switch (bc.kind) {
+        case 3:   // fixed depth
+            hr = bc.value;
+            break;
+        case 4:   // fixed water-surface elevation
+            hr = fmax(bc.value - L.z, 0.0);
+            break;
+        case 1:   // transmissive
+            solve = false;
+            G0 = L.h * unl;
+            G1 = G0 * unl + 0.5 * g * L.h * L.h;
+            G2 = G0 * utl;
+            break;
+        case 2:   // inflow
+            solve = false;
+            G0 = -bc.q;
+            G1 = (L.h > h_dry ? bc.q * bc.q / L.h : 0.0) +
+                 0.5 * g * L.h * L.h;
+            G2 = 0.0;
+            break;
+        default:  // wall
+            solve = false;
+            G0 = 0.0;
+            G1 = 0.5 * g * L.h * L.h;
+            G2 = 0.0;
+            break;
+        }
+    }
+    if (solve) hllc(g, h_dry, hl, unl, utl, hr, unr, utr, G0, G1, G2);
     const double F1 = G1 * nx - G2 * ny;
     const double F2 = G1 * ny + G2 * nx;
-    const double pl = 0.5 * g * (hl * hl - L.h * L.h);
-    const double pr = 0.5 * g * (hr * hr - R.h * R.h);
-    cl[0] = -len * G0;
-    cl[1] = len * (pl * nx - F1);
-    cl[2] = len * (pl * ny - F2);
-    cr[0] = len * G0;
-    cr[1] = len * (F1 - pr * nx);
-    cr[2] = len * (F2 - pr * ny);
-}
-
-// Contribution of a boundary edge of cell L (outward normal n): wall,
-// transmissive, inflow of discharge q per unit length, or a ghost state of
-// fixed depth / fixed surface elevation with the cell's velocity.
-__device__ __forceinline__ void boundary_edge(double g, double h_dry,
-                                              const BcEntry &bc,
-                                              const CellState &L, double nx,
-                                              double ny, double len,
-                                              double cl[3])
-{
-    const double un = L.u * nx + L.v * ny, ut = -L.u * ny + L.v * nx;
-    double G0, G1, G2;
-    switch (bc.kind) {
-    case 1:   // transmissive
-        G0 = L.h * un;
-        G1 = G0 * un + 0.5 * g * L.h * L.h;
-        G2 = G0 * ut;
-        break;
-    case 2:   // inflow
-        G0 = -bc.q;
-        G1 = (L.h > h_dry ? bc.q * bc.q / L.h : 0.0) + 0.5 * g * L.h * L.h;
-        G2 = 0.0;
-        break;
-    case 3:   // fixed depth
-        hllc(g, h_dry, L.h, un, ut, bc.value, un, ut, G0, G1, G2);
-        break;
-    case 4:   // fixed water-surface elevation
-        hllc(g, h_dry, L.h, un, ut, fmax(bc.value - L.z, 0.0), un, ut, G0,
-             G1, G2);
-        break;
-    default:  // wall
-        G0 = 0.0;
-        G1 = 0.5 * g * L.h * L.h;
-        G2 = 0.0;
-        break;
+    if (!bnd) {
+        const double pl = 0.5 * g * (hl * hl - L.h * L.h);
+        const double pr = 0.5 * g * (hr * hr - R.h * R.h);
+        cl0 = -len * G0;
+        cl1 = len * (pl * nx - F1);
+        cl2 = len * (pl * ny - F2);
+        cr0 = len * G0;
+        cr1 = len * (F1 - pr * nx);
+        cr2 = len * (F2 - pr * ny);
+    } else {
+        cl0 = -len * G0;
+        cl1 = -len * F1;
+        cl2 = -len * F2;
+        cr0 = 0.0;
+        cr1 = 0.0;
+        cr2 = 0.0;
     }
-    cl[0] = -len * G0;
-    cl[1] = -len * (G1 * nx - G2 * ny);
-    cl[2] = -len * (G1 * ny + G2 * nx);
 }
 
 // Update of one cell from the sum R of its three edge contributions:
 // dh = dt R_h / A; the semi-implicit Manning solve for dq (eqs. 33-37);
 // positivity. `clamp` returns the mass added by the positivity fix.
 __device__ __forceinline__ void cell_update(double h_dry, double dt, double A,
-                                            const double *gm2, double h,
-                                            double hu, double hv, double R0,
-                                            double R1, double R2, double &hn,
-                                            double &hun, double &hvn,
-                                            double &clamp)
+                                            double gm2, double h, double hu,
+                                            double hv, double R0, double R1,
+                                            double R2, double &hn, double &hun,
+                                            double &hvn, double &clamp)
 {
     const double bh = R0 / A, bx = R1 / A, by = R2 / A;
     const double dh = dt * bh;
@@ -222,7 +238,7 @@ __device__ __forceinline__ void cell_update(double h_dry, double dt, double A,
     if (h > h_dry && qn > 0.0) {
         // semi-implicit Manning: S_f = -c|q|q, c = g m^2 h^(-7/3);
         // (I - dt/2 dS/dq) dq = dt (R_q/A + S_f) + dt/2 (dS/dh) dh
-        const double c = *gm2 / (h * h * cbrt(h));
+        const double c = gm2 / (h * h * cbrt(h));
         const double sfx = -c * qn * hu, sfy = -c * qn * hv;
         const double jhx = (7.0 / 3.0) * c * qn * hu / h;
         const double jhy = (7.0 / 3.0) * c * qn * hv / h;
@@ -300,7 +316,7 @@ __device__ __forceinline__ void block_finish(const StepArgs &a, int blk,
             anybad |= red_bad[w];
         }
         if (m < INFINITY)
-            atomicMin(&a.clock->minrs[nxt],
+            atomicMin(&a.clock->minrs[nxt][blockIdx.x & (kClockLanes - 1)][0],
                       (unsigned long long)__double_as_longlong(m));
         if (cs != 0.0) a.ledger[blk] += cs;
         if (anybad || unbounded) {
@@ -312,20 +328,67 @@ __device__ __forceinline__ void block_finish(const StepArgs &a, int blk,
             a.clock->t[nxt] = tn;
             a.clock->last_dt = dt;
             if (dt > 0.0) a.clock->steps += 1;
-            atomicExch(&a.clock->minrs[nn], kInfBits);
+            for (int x = 0; x < kClockLanes; ++x)
+                atomicExch(&a.clock->minrs[nn][x][0], kInfBits);
         }
     }
 }
 
-// NC cells per block, NT threads (NC or 2 NC): threads below NC own a cell;
-// all NT threads share the block's edges. Loads follow the phases and skip
-// inputs that cannot change the result: the geometry of an interior edge
-// whose two cells hold no water at all (h == 0: its flux and bed-slope terms
-// are zero), or of a wall / transmissive edge of such a cell, and the area of
-// a cell at or below h_dry whose three edges bring exactly nothing (then
-// R/A = R). The friction coefficient and inscribed radius are read only by
-// wet cells.
-template <int NC, int NT>
+// Decoded side of a block edge (see BlockMesh::be_a / be_b).
+struct Side {
+    int kind;      // 0 cell of this block, 1 cell of another block, 2 boundary
+    int local;     // kind 0: local cell index
+    int k;         // kind 0: that cell's side along the edge
+    int global;    // kind 1: internal cell index; kind 2: boundary tag
+};
+
+__device__ __forceinline__ Side decode_side(int32_t v)
+{
+    Side s;
+    const uint32_t u = uint32_t(v);
+    if (u & kSideLocal) {
+        s.kind = 0;
+        s.local = int(u & 0xfffu);
+        s.k = int((u >> 12) & 3u);
+        s.global = 0;
+    } else if (u & kSideBoundary) {
+        s.kind = 2;
+        s.local = 0;
+        s.k = 0;
+        s.global = int(u & 0x3ffu);
+    } else {
+        s.kind = 1;
+        s.local = 0;
+        s.k = 0;
+        s.global = v;
+    }
+    return s;
+}
+
+// Minimum of R/s over the XCD slots of one clock slot.
+__device__ __forceinline__ double clock_min_rs(const Clock *c, int slot)
+{
+    double m = __longlong_as_double((long long)c->minrs[slot][0][0]);
+#pragma unroll
+    for (int x = 1; x < kClockLanes; ++x)
+        m = fmin(m, __longlong_as_double((long long)c->minrs[slot][x][0]));
+    return m;
+}
+
+// One explicit step for one block of NC consecutive cells, NT threads (NC or
+// 2 NC); threads below NC own a cell, all threads share the block's edges.
+//   phase 1: load the owned cell, the thread's edge record and the state
+//            of that edge's neighbour in another block, all before the
+//            first barrier; stage (h, u, v, z) in LDS;
+//   phase 2: evaluate the edge; its contributions go straight into the LDS
+//            slots [component][side][cell] of the one or two cells of this
+//            block it bounds. An edge between two cells holding no water
+//            (h == 0), or a wall / transmissive edge of such a cell, adds
+//            exact zeros and its geometry is not read (GEOM: read always);
+//   phase 3: each cell sums its three sides in side order, updates, writes
+//            U^{n+1} and R_i / s_i; block reductions; clock.
+// A dry cell whose three sides bring exact zeros needs no area (R/A = R).
+template <int NC, int NT, bool GEOM>
 __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
 {
     extern __shared__ double lds[];
@@ -336,8 +399,7 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
     double *s_u = s_h + NC;
     double *s_v = s_u + NC;
     double *s_z = s_v + NC;
-    double *s_c = s_z + NC;   // 6 x emax: left contributions, then right
-    const int emax = a.emax;
+    double *s_c = s_z + NC;   // [3 components][3 sides][NC cells]
 
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int c0 = a.blk_cell[blk];
@@ -347,191 +409,38 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
     const int tid = threadIdx.x;
     const double g = a.g, h_dry = a.h_dry;
 
-    // time step of this step: CFL * min R/s of U^n, bounded, clipped to t_end
-    const int cur = a.cur;
-    const int nxt = cur == 2 ? 0 : cur + 1;
-    const double mrs = __longlong_as_double((long long)a.clock->minrs[cur]);
-    const double t = a.clock->t[cur];
-    double dt = fmin(a.cfl * mrs, a.dt_max);
-    const double rem = a.t_end - t;
-    double tn;
-    if (dt >= rem) {
-        dt = rem > 0.0 ? rem : 0.0;
-        tn = rem > 0.0 ? a.t_end : t;
-    } else {
-        tn = t + dt;
-    }
-    const bool unbounded = !(dt < INFINITY);
-    if (unbounded) {
-        dt = 0.0;
-        tn = t;
-    }
-
-    // stage this block's cells
-    const bool own = tid < NC && tid < nc;
-    const int i = c0 + tid;
-    double h = 0.0, hu = 0.0, hv = 0.0;
-    if (own) {
-        h = a.h0[i];
-        hu = a.hu0[i];
-        hv = a.hv0[i];
-        s_h[tid] = h;
-        s_z[tid] = a.z[i];
-        if (h > h_dry) {
-            s_u[tid] = hu / h;
-            s_v[tid] = hv / h;
-        } else {
-            s_u[tid] = 0.0;
-            s_v[tid] = 0.0;
-        }
-    }
-    __syncthreads();
-
-    // every edge of the block once
-    for (int k = tid; k < ne; k += NT) {
-        const int l = a.be_left[e0 + k];
-        const int r = a.be_right[e0 + k];
-        CellState L, R;
-        const unsigned ll = unsigned(l - c0);
-        if (ll < unsigned(nc)) {
-            L.h = s_h[ll]; L.u = s_u[ll]; L.v = s_v[ll]; L.z = s_z[ll];
-        } else {
-            L = load_cell(a, l);
-        }
-        BcEntry bc{};
-        bool idle;
-        if (r >= 0) {
-            const unsigned rr = unsigned(r - c0);
-            if (rr < unsigned(nc)) {
-                R.h = s_h[rr]; R.u = s_u[rr]; R.v = s_v[rr]; R.z = s_z[rr];
-            } else {
-                R = load_cell(a, r);
-            }
-            idle = L.h == 0.0 && R.h == 0.0;
-        } else {
-            bc = a.bc[-1 - r];
-            idle = L.h == 0.0 && (bc.kind == 0 || bc.kind == 1);
-        }
-        double cl[3] = {0.0, 0.0, 0.0}, cr[3] = {0.0, 0.0, 0.0};
-        if (!idle) {
-            const double nx = a.be_nx[e0 + k];
-            const double ny = a.be_ny[e0 + k];
-            const double len = a.be_len[e0 + k];
-            if (r >= 0)
-                interior_edge(g, h_dry, L, R, nx, ny, len, cl, cr);
-            else
-                boundary_edge(g, h_dry, bc, L, nx, ny, len, cl);
-        }
-        s_c[k] = cl[0];
-        s_c[emax + k] = cl[1];
-        s_c[2 * emax + k] = cl[2];
-        s_c[3 * emax + k] = cr[0];
-        s_c[4 * emax + k] = cr[1];
-        s_c[5 * emax + k] = cr[2];
-    }
-    __syncthreads();
-
-    // cell update
-    double rs = INFINITY, clamp = 0.0;
-    unsigned bad = 0;
-    if (own) {
-        const unsigned long long pk = a.slots[i];
-        double R0 = 0.0, R1 = 0.0, R2 = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const unsigned s = unsigned(pk >> (16 * k)) & 0xffffu;
-            const double *src = s_c + (s >> 15) * 3 * emax + (s & 0x7fffu);
-            R0 += src[0];
-            R1 += src[emax];
-            R2 += src[2 * emax];
-        }
-        double hn = h, hun = hu, hvn = hv;
-        if (dt > 0.0) {
-            if (h <= h_dry && R0 == 0.0 && R1 == 0.0 && R2 == 0.0) {
-                // R/A = R exactly; no friction below h_dry; h + dt*(+-0)
-                // cannot go negative
-                hn = h + dt * R0;
-                hun = 0.0;
-                hvn = 0.0;
-            } else {
-                cell_update(h_dry, dt, a.area[i], a.gm2 + i, h, hu, hv, R0,
-                            R1, R2, hn, hun, hvn, clamp);
-            }
-        }
-        a.h1[i] = hn;
-        a.hu1[i] = hun;
-        a.hv1[i] = hvn;
-        if (!isfinite(hn) || !isfinite(hun) || !isfinite(hvn)) bad = 1u;
-        if (hn > h_dry) {
-            const double u = hun / hn, v = hvn / hn;
-            rs = a.inradius[i] / (sqrt(g * hn) + sqrt(u * u + v * v));
-        }
-    }
-    block_finish<NT>(a, blk, rs, clamp, bad, unbounded, dt, tn, nxt,
-                     red_min, red_sum, red_bad);
-}
-
-// Same step with every independent load issued before the first barrier:
-// the owned cell's state and per-cell data, the thread's edge record, and then
-// (depending only on that record) the state of a neighbour in another block.
-// A block then waits for two memory round trips instead of four.
-template <int NC, int NT>
-__global__ __launch_bounds__(NT) void swe_step_kernel_pf(StepArgs a)
-{
-    extern __shared__ double lds[];
-    __shared__ double red_min[NT / 64];
-    __shared__ double red_sum[NT / 64];
-    __shared__ unsigned red_bad[NT / 64];
-    double *s_h = lds;
-    double *s_u = s_h + NC;
-    double *s_v = s_u + NC;
-    double *s_z = s_v + NC;
-    double *s_c = s_z + NC;   // 6 x emax: left contributions, then right
-    const int emax = a.emax;
-
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int c0 = a.blk_cell[blk];
-    const int nc = a.blk_cell[blk + 1] - c0;
-    const int e0 = a.blk_edge[blk];
-    const int ne = a.blk_edge[blk + 1] - e0;
-    const int tid = threadIdx.x;
-    const double g = a.g, h_dry = a.h_dry;
-
-    // loads, all issued up front
+    // ---- phase 1: loads
     const bool own = tid < NC && tid < nc;
     const int i = c0 + tid;
     double h = 0.0, hu = 0.0, hv = 0.0, zc = 0.0;
-    double A = 1.0, gm2 = 0.0, inr = 0.0;
-    unsigned long long pk = 0;
     if (own) {
         h = a.h0[i];
         hu = a.hu0[i];
         hv = a.hv0[i];
         zc = a.z[i];
-        pk = a.slots[i];
-        A = a.area[i];
-        gm2 = a.gm2[i];
-        inr = a.inradius[i];
     }
     const bool has_edge = tid < ne;
-    int l = 0, r = 0;
+    int32_t ea = 0, eb = 0;
     double nx = 0.0, ny = 0.0, len = 0.0;
     if (has_edge) {
-        l = a.be_left[e0 + tid];
-        r = a.be_right[e0 + tid];
-        nx = a.be_nx[e0 + tid];
-        ny = a.be_ny[e0 + tid];
-        len = a.be_len[e0 + tid];
+        ea = a.be_a[e0 + tid];
+        eb = a.be_b[e0 + tid];
+        if (GEOM) {
+            nx = a.be_nx[e0 + tid];
+            ny = a.be_ny[e0 + tid];
+            len = a.be_len[e0 + tid];
+        }
     }
-    const bool l_in = unsigned(l - c0) < unsigned(nc);
-    const bool r_in = r >= 0 && unsigned(r - c0) < unsigned(nc);
-    // the one side (if any) that lies in another block
+    // the edge's neighbour in another block: a side coded as a plain
+    // (non-negative, below kSideBoundary) internal index
     CellState X;
     X.h = 0.0; X.u = 0.0; X.v = 0.0; X.z = 0.0;
     double xhu = 0.0, xhv = 0.0;
-    const bool need_x = has_edge && (!l_in || (r >= 0 && !r_in));
+    const bool xa = uint32_t(ea) < kSideBoundary;
+    const bool xb = uint32_t(eb) < kSideBoundary;
+    const bool need_x = has_edge && (xa || xb);
     if (need_x) {
-        const int x = l_in ? r : l;
+        const int x = xa ? ea : eb;
         X.h = a.h0[x];
         xhu = a.hu0[x];
         xhv = a.hv0[x];
@@ -541,7 +450,7 @@ __global__ __launch_bounds__(NT) void swe_step_kernel_pf(StepArgs a)
     // time step of this step: CFL * min R/s of U^n, bounded, clipped to t_end
     const int cur = a.cur;
     const int nxt = cur == 2 ? 0 : cur + 1;
-    const double mrs = __longlong_as_double((long long)a.clock->minrs[cur]);
+    const double mrs = clock_min_rs(a.clock, cur);
     const double t = a.clock->t[cur];
     double dt = fmin(a.cfl * mrs, a.dt_max);
     const double rem = a.t_end - t;
@@ -558,7 +467,6 @@ __global__ __launch_bounds__(NT) void swe_step_kernel_pf(StepArgs a)
         tn = t;
     }
 
-    // stage this block's cells
     if (own) {
         s_h[tid] = h;
         s_z[tid] = zc;
@@ -576,94 +484,102 @@ __global__ __launch_bounds__(NT) void swe_step_kernel_pf(StepArgs a)
     }
     __syncthreads();
 
-    // every edge of the block once
-    if (has_edge) {
-        CellState L, R;
-        if (l_in) {
-            const int ll = l - c0;
-            L.h = s_h[ll]; L.u = s_u[ll]; L.v = s_v[ll]; L.z = s_z[ll];
-        } else {
-            L = X;
-        }
-        double cl[3], cr[3];
-        if (r >= 0) {
-            if (r_in) {
-                const int rr = r - c0;
-                R.h = s_h[rr]; R.u = s_u[rr]; R.v = s_v[rr]; R.z = s_z[rr];
-            } else {
-                R = X;
+    // ---- phase 2: edges
+    for (int k = tid; k < ne; k += NT) {
+        Side pa = decode_side(ea), pb = decode_side(eb);
+        CellState Y = X;
+        double qx = nx, qy = ny, ql = len;
+        if (k != tid) {               // blocks with more than NT edges
+            pa = decode_side(a.be_a[e0 + k]);
+            pb = decode_side(a.be_b[e0 + k]);
+            if (pa.kind == 1) Y = load_cell(a, pa.global);
+            if (pb.kind == 1) Y = load_cell(a, pb.global);
+            if (GEOM) {
+                qx = a.be_nx[e0 + k];
+                qy = a.be_ny[e0 + k];
+                ql = a.be_len[e0 + k];
             }
-            interior_edge(g, h_dry, L, R, nx, ny, len, cl, cr);
-        } else {
-            const BcEntry bc = a.bc[-1 - r];
-            boundary_edge(g, h_dry, bc, L, nx, ny, len, cl);
-            cr[0] = 0.0; cr[1] = 0.0; cr[2] = 0.0;
         }
-        s_c[tid] = cl[0];
-        s_c[emax + tid] = cl[1];
-        s_c[2 * emax + tid] = cl[2];
-        s_c[3 * emax + tid] = cr[0];
-        s_c[4 * emax + tid] = cr[1];
-        s_c[5 * emax + tid] = cr[2];
-    }
-    for (int k = tid + NT; k < ne; k += NT) {   // blocks with > NT edges
-        const int l2 = a.be_left[e0 + k];
-        const int r2 = a.be_right[e0 + k];
         CellState L, R;
-        if (unsigned(l2 - c0) < unsigned(nc)) {
-            const int ll = l2 - c0;
-            L.h = s_h[ll]; L.u = s_u[ll]; L.v = s_v[ll]; L.z = s_z[ll];
+        R.h = 0.0; R.u = 0.0; R.v = 0.0; R.z = 0.0;
+        if (pa.kind == 0) {
+            L.h = s_h[pa.local]; L.u = s_u[pa.local];
+            L.v = s_v[pa.local]; L.z = s_z[pa.local];
         } else {
-            L = load_cell(a, l2);
+            L = Y;
         }
-        double cl[3], cr[3];
-        if (r2 >= 0) {
-            if (unsigned(r2 - c0) < unsigned(nc)) {
-                const int rr = r2 - c0;
-                R.h = s_h[rr]; R.u = s_u[rr]; R.v = s_v[rr]; R.z = s_z[rr];
+        bool idle;
+        BcEntry pbc{};
+        if (pb.kind == 2) {
+            pbc = a.bc[pb.global];
+            idle = L.h == 0.0 && (pbc.kind == 0 || pbc.kind == 1);
+        } else {
+            if (pb.kind == 0) {
+                R.h = s_h[pb.local]; R.u = s_u[pb.local];
+                R.v = s_v[pb.local]; R.z = s_z[pb.local];
             } else {
-                R = load_cell(a, r2);
+                R = Y;
             }
-            interior_edge(g, h_dry, L, R, a.be_nx[e0 + k], a.be_ny[e0 + k],
-                          a.be_len[e0 + k], cl, cr);
-        } else {
-            const BcEntry bc = a.bc[-1 - r2];
-            boundary_edge(g, h_dry, bc, L, a.be_nx[e0 + k], a.be_ny[e0 + k],
-                          a.be_len[e0 + k], cl);
-            cr[0] = 0.0; cr[1] = 0.0; cr[2] = 0.0;
+            idle = L.h == 0.0 && R.h == 0.0;
         }
-        s_c[k] = cl[0];
-        s_c[emax + k] = cl[1];
-        s_c[2 * emax + k] = cl[2];
-        s_c[3 * emax + k] = cr[0];
-        s_c[4 * emax + k] = cr[1];
-        s_c[5 * emax + k] = cr[2];
+        double cl0 = 0.0, cl1 = 0.0, cl2 = 0.0;
+        double cr0 = 0.0, cr1 = 0.0, cr2 = 0.0;
+        if (!idle) {
+            if (!GEOM) {
+                qx = a.be_nx[e0 + k];
+                qy = a.be_ny[e0 + k];
+                ql = a.be_len[e0 + k];
+            }
+            edge_contrib(g, h_dry, pb.kind == 2, pbc, L, R, qx, qy, ql, cl0,
+                         cl1, cl2, cr0, cr1, cr2);
+        }
+        if (pa.kind == 0) {
+            double *d = s_c + pa.k * NC + pa.local;
+            d[0] = cl0;
+            d[3 * NC] = cl1;
+            d[6 * NC] = cl2;
+        }
+        if (pb.kind == 0) {
+            double *d = s_c + pb.k * NC + pb.local;
+            d[0] = cr0;
+            d[3 * NC] = cr1;
+            d[6 * NC] = cr2;
+        }
     }
     __syncthreads();
 
-    // cell update
+    // ---- phase 3: cells
     double rs = INFINITY, clamp = 0.0;
     unsigned bad = 0;
     if (own) {
         double R0 = 0.0, R1 = 0.0, R2 = 0.0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const unsigned s = unsigned(pk >> (16 * k)) & 0xffffu;
-            const double *src = s_c + (s >> 15) * 3 * emax + (s & 0x7fffu);
-            R0 += src[0];
-            R1 += src[emax];
-            R2 += src[2 * emax];
+            R0 += s_c[k * NC + tid];
+            R1 += s_c[(3 + k) * NC + tid];
+            R2 += s_c[(6 + k) * NC + tid];
         }
         double hn = h, hun = hu, hvn = hv;
         if (dt > 0.0) {
-            cell_update(h_dry, dt, A, &gm2, h, hu, hv, R0, R1, R2, hn, hun,
-                        hvn, clamp);
+            if (h <= h_dry && R0 == 0.0 && R1 == 0.0 && R2 == 0.0) {
+                // R/A = R exactly; no friction below h_dry; h + dt*(+-0)
+                // cannot go negative
+                hn = h + dt * R0;
+                hun = 0.0;
+                hvn = 0.0;
+            } else {
+                const double A = a.area[i];
+                const double gm2 = h > h_dry ? a.gm2[i] : 0.0;
+                cell_update(h_dry, dt, A, gm2, h, hu, hv, R0, R1, R2, hn,
+                            hun, hvn, clamp);
+            }
         }
         a.h1[i] = hn;
         a.hu1[i] = hun;
         a.hv1[i] = hvn;
         if (!isfinite(hn) || !isfinite(hun) || !isfinite(hvn)) bad = 1u;
         if (hn > h_dry) {
+            const double inr = a.inradius[i];
             const double u = hun / hn, v = hvn / hn;
             rs = inr / (sqrt(g * hn) + sqrt(u * u + v * v));
         }
@@ -678,9 +594,8 @@ __global__ void clock_set_kernel(Clock *c, double t, long long steps)
         c->t[0] = t;
         c->t[1] = t;
         c->t[2] = t;
-        c->minrs[0] = kInfBits;
-        c->minrs[1] = kInfBits;
-        c->minrs[2] = kInfBits;
+        for (int s = 0; s < 3; ++s)
+            for (int x = 0; x < kClockLanes; ++x) c->minrs[s][x][0] = kInfBits;
         c->last_dt = 0.0;
         c->steps = steps;
         c->health = 0u;
@@ -691,7 +606,9 @@ __global__ void clock_set_kernel(Clock *c, double t, long long steps)
 
 __global__ void slot_reset_kernel(Clock *c, int slot)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) atomicExch(&c->minrs[slot], kInfBits);
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        for (int x = 0; x < kClockLanes; ++x)
+            atomicExch(&c->minrs[slot][x][0], kInfBits);
 }
 
 __global__ __launch_bounds__(256) void min_rs_kernel(
@@ -715,7 +632,8 @@ __global__ __launch_bounds__(256) void min_rs_kernel(
     if (threadIdx.x == 0) {
         double m = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
         if (m < INFINITY)
-            atomicMin(&c->minrs[cur], (unsigned long long)__double_as_longlong(m));
+            atomicMin(&c->minrs[cur][blockIdx.x & (kClockLanes - 1)][0],
+                      (unsigned long long)__double_as_longlong(m));
     }
 }
 
@@ -843,20 +761,21 @@ inline unsigned grid_for(int64_t n, int threads = 256)
 
 }  // namespace
 
-size_t step_lds_bytes(int block_cells, int emax)
+size_t step_lds_bytes(int block_cells)
 {
-    return sizeof(double) * (4 * size_t(block_cells) + 6 * size_t(emax));
+    return sizeof(double) * 13 * size_t(block_cells);
 }
 
 namespace {
 template <int NC, int NT>
-void launch_one(const StepArgs &a, size_t lds, int schedule, hipStream_t s)
+void launch_one(const StepArgs &a, int schedule, hipStream_t s)
 {
+    const size_t lds = step_lds_bytes(NC);
     if (schedule == 0)
-        hipLaunchKernelGGL((swe_step_kernel<NC, NT>), dim3(a.n_blocks),
+        hipLaunchKernelGGL((swe_step_kernel<NC, NT, false>), dim3(a.n_blocks),
                            dim3(NT), lds, s, a);
     else
-        hipLaunchKernelGGL((swe_step_kernel_pf<NC, NT>), dim3(a.n_blocks),
+        hipLaunchKernelGGL((swe_step_kernel<NC, NT, true>), dim3(a.n_blocks),
                            dim3(NT), lds, s, a);
 }
 }  // namespace
@@ -864,25 +783,24 @@ void launch_one(const StepArgs &a, size_t lds, int schedule, hipStream_t s)
 hipError_t launch_step(const StepArgs &a, int block_cells, int threads,
                        int schedule, hipStream_t s)
 {
-    const size_t lds = step_lds_bytes(block_cells, a.emax);
     const bool twice = threads == 2 * block_cells;
     if (!twice && threads != block_cells) return hipErrorInvalidValue;
     switch (block_cells) {
     case 64:
-        twice ? launch_one<64, 128>(a, lds, schedule, s)
-              : launch_one<64, 64>(a, lds, schedule, s);
+        twice ? launch_one<64, 128>(a, schedule, s)
+              : launch_one<64, 64>(a, schedule, s);
         break;
     case 128:
-        twice ? launch_one<128, 256>(a, lds, schedule, s)
-              : launch_one<128, 128>(a, lds, schedule, s);
+        twice ? launch_one<128, 256>(a, schedule, s)
+              : launch_one<128, 128>(a, schedule, s);
         break;
     case 256:
-        twice ? launch_one<256, 512>(a, lds, schedule, s)
-              : launch_one<256, 256>(a, lds, schedule, s);
+        twice ? launch_one<256, 512>(a, schedule, s)
+              : launch_one<256, 256>(a, schedule, s);
         break;
     case 512:
-        twice ? launch_one<512, 1024>(a, lds, schedule, s)
-              : launch_one<512, 512>(a, lds, schedule, s);
+        twice ? launch_one<512, 1024>(a, schedule, s)
+              : launch_one<512, 512>(a, schedule, s);
         break;
     default:
         return hipErrorInvalidValue;

@@ -388,14 +388,12 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
     M.n_edges = ne;
     M.n_bnd_edges = nb;
     M.area.resize(nc);
-    M.inv_area.resize(nc);
     M.inradius.resize(nc);
     double rmin = INFINITY;
 #pragma omp parallel for schedule(static) reduction(min : rmin)
     for (int64_t i = 0; i < nc; ++i) {
         const int32_t u = order[i];
         M.area[i] = area[u];
-        M.inv_area[i] = 1.0 / area[u];
         M.inradius[i] = inr[u];
         rmin = std::min(rmin, inr[u]);
     }
@@ -406,14 +404,22 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
     // ---- blocks of block_cells consecutive internal cells and their edges:
     //      edges with both cells in the block first, then edges to another
     //      block, then boundary edges; each group in order of first use (an
-    //      edge inside the block is first used by its lower-numbered cell)
+    //      edge inside the block is first used by its lower-numbered cell).
+    //      Each side of a block edge is encoded as
+    //        in the block:  kSideLocal | k << 12 | local cell   (k = the
+    //                       cell's side along this edge, 0..2)
+    //        other block:   internal cell index (< 2^30)
+    //        boundary:      kSideBoundary | tag   (right side only)
     const int32_t B = block_cells;
     const int64_t nblk = (nc + B - 1) / B;
+    if (nc >= (int64_t(1) << 30)) {
+        err = "mesh too large: at most 2^30 cells";
+        return false;
+    }
     M.block_cells = B;
     M.n_blocks = int32_t(nblk);
     M.blk_cell.resize(nblk + 1);
     M.blk_edge.assign(nblk + 1, 0);
-    M.slots.assign(nc, 0);
     const std::vector<int32_t> &iou = M.internal_of_user;
     // edge and neighbour (internal index, -1 on the boundary) of side k of
     // internal cell i, gathered once in internal order
@@ -429,10 +435,6 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
                                : iou[e_left[e] == u ? e_right[e] : e_left[e]];
         }
     }
-    auto other = [&](int64_t i, int k, int32_t &e) -> int64_t {
-        e = side_e[3 * i + k];
-        return side_nb[3 * i + k];
-    };
     int32_t emax = 0;
 #pragma omp parallel for schedule(static) reduction(max : emax)
     for (int64_t b = 0; b < nblk; ++b) {
@@ -440,8 +442,7 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
         int32_t n = 0;
         for (int64_t i = c0; i < c1; ++i)
             for (int k = 0; k < 3; ++k) {
-                int32_t e;
-                const int64_t j = other(i, k, e);
+                const int64_t j = side_nb[3 * i + k];
                 if (j < 0 || j < c0 || j >= c1 || i < j) ++n;
             }
         M.blk_cell[b] = int32_t(c0);
@@ -450,66 +451,55 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
     }
     M.blk_cell[nblk] = int32_t(nc);
     for (int64_t b = 0; b < nblk; ++b) M.blk_edge[b + 1] += M.blk_edge[b];
-    if (emax >= (1 << 15)) {
-        err = "block edge list too long";
-        return false;
-    }
     M.max_block_edges = emax;
     const int64_t nbe = M.blk_edge[nblk];
-    M.be_left.resize(nbe);
-    M.be_right.resize(nbe);
+    M.be_a.resize(nbe);
+    M.be_b.resize(nbe);
     M.be_nx.resize(nbe);
     M.be_ny.resize(nbe);
     M.be_len.resize(nbe);
-    std::vector<int32_t> inner_slot(ne, 0);
 #pragma omp parallel
     {
-        struct Use { int32_t e; int32_t side; };   // side = 3 * local + k
+        struct Use { int64_t i; int k; int32_t e; };
         std::vector<Use> grp[3];
-        std::vector<int32_t> side_slot(3 * B);
 #pragma omp for schedule(static)
         for (int64_t b = 0; b < nblk; ++b) {
             const int64_t c0 = b * B, c1 = std::min<int64_t>(nc, c0 + B);
             for (auto &g : grp) g.clear();
-            std::fill(side_slot.begin(), side_slot.end(), -1);
             for (int64_t i = c0; i < c1; ++i)
                 for (int k = 0; k < 3; ++k) {
-                    int32_t e;
-                    const int64_t j = other(i, k, e);
-                    const Use use{e, int32_t(3 * (i - c0) + k)};
+                    const int64_t j = side_nb[3 * i + k];
+                    const Use use{i, k, side_e[3 * i + k]};
                     if (j < 0) grp[2].push_back(use);
                     else if (j < c0 || j >= c1) grp[1].push_back(use);
                     else if (i < j) grp[0].push_back(use);
                 }
-            int32_t s = 0;
+            // side code of internal cell j in this block along edge e
+            auto local_code = [&](int64_t j, int32_t e) {
+                int kk = 0;
+                while (side_e[3 * j + kk] != e) ++kk;
+                return int32_t(kSideLocal | (uint32_t(kk) << 12) |
+                               uint32_t(j - c0));
+            };
             int64_t at = M.blk_edge[b];
             for (int g = 0; g < 3; ++g)
                 for (const Use &use : grp[g]) {
                     const int32_t e = use.e;
-                    side_slot[use.side] = s;
-                    if (g == 0) inner_slot[e] = s;
-                    M.be_left[at] = iou[e_left[e]];
-                    M.be_right[at] = e_right[e] >= 0 ? iou[e_right[e]]
-                                                     : -1 - e_tag[e];
+                    const int64_t il = iou[e_left[e]];
+                    const bool l_in = il >= c0 && il < c1;
+                    M.be_a[at] = l_in ? local_code(il, e) : int32_t(il);
+                    if (e_right[e] < 0) {
+                        M.be_b[at] = int32_t(kSideBoundary | uint32_t(e_tag[e]));
+                    } else {
+                        const int64_t ir = iou[e_right[e]];
+                        const bool r_in = ir >= c0 && ir < c1;
+                        M.be_b[at] = r_in ? local_code(ir, e) : int32_t(ir);
+                    }
                     M.be_nx[at] = enx[e];
                     M.be_ny[at] = eny[e];
                     M.be_len[at] = elen[e];
                     ++at;
-                    ++s;
                 }
-            for (int64_t i = c0; i < c1; ++i) {
-                const int32_t u = order[i];
-                uint64_t pack = 0;
-                for (int k = 0; k < 3; ++k) {
-                    int32_t e;
-                    other(i, k, e);
-                    int32_t slot = side_slot[3 * (i - c0) + k];
-                    if (slot < 0) slot = inner_slot[e];
-                    const uint64_t right = (e_right[e] == u) ? 1u : 0u;
-                    pack |= (uint64_t(slot) | (right << 15)) << (16 * k);
-                }
-                M.slots[i] = pack;
-            }
         }
     }
     return true;

@@ -10,6 +10,9 @@
 
 namespace swe {
 
+constexpr uint32_t kSideLocal = 0x80000000u;
+constexpr uint32_t kSideBoundary = 0x40000000u;
+
 // Device-facing mesh in the internal (locality) cell order.
 struct BlockMesh {
     int64_t n_nodes = 0, n_cells = 0, n_edges = 0, n_bnd_edges = 0;
@@ -22,18 +25,20 @@ struct BlockMesh {
     std::vector<int32_t> internal_of_user, user_of_internal;
 
     // per internal cell
-    std::vector<double> area, inv_area, inradius;
-    std::vector<uint64_t> slots;   // 3 x 16 bits: block-edge slot | side<<15
+    std::vector<double> area, inradius;
 
     // per block: [blk_cell[b], blk_cell[b+1]) cells,
     //            [blk_edge[b], blk_edge[b+1]) block-edge records
     std::vector<int32_t> blk_cell, blk_edge;
 
-    // per block-edge record
-    //   left  : internal index of the cell on the left of the edge
-    //   right : internal index of the right cell, or -1 - tag on the boundary
-    //   n     : unit normal from left to right (outward on the boundary)
-    std::vector<int32_t> be_left, be_right;
+    // per block-edge record: the edge's left side (be_a) and right side
+    // (be_b), each coded as
+    //   kSideLocal | k << 12 | c : cell c of the block (local index), whose
+    //                              local side k is this edge
+    //   i (>= 0, < 2^30)         : internal index of a cell of another block
+    //   kSideBoundary | tag      : boundary (right side only)
+    // and the unit normal from left to right (outward on the boundary).
+    std::vector<int32_t> be_a, be_b;
     std::vector<double> be_nx, be_ny, be_len;
 
     // total boundary length per tag (inflow discharge per unit length)
