@@ -80,10 +80,11 @@ typedef struct {
                               0: keep the user order; next set_mesh           */
     int32_t block_threads; /* threads per block: block_cells, 2*block_cells,
                               or 0 = automatic (= block_cells) (0)            */
-    int32_t load_schedule; /* 0: loads per phase, skipping inputs that cannot
-                              change the result on dry cells (default);
-                              1: every load issued before the first barrier.
-                              Same results; a tuning switch                   */
+    int32_t load_schedule; /* 0: edge and cell geometry read only where it
+                              can change the result (not between cells
+                              holding no water) (default); 1: all geometry
+                              requested with the state, before the first
+                              barrier. Same results; a tuning switch          */
     int32_t reserved;      /* must be 0                                       */
 } swe_params;
 

@@ -30,7 +30,8 @@ HIP_FLAGS = [
 ]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=off",
               "-fopenmp",
-              "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include"]
+              "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include",
+              f"-I{os.path.join(ROOT, 'include')}"]
 
 
 def _run(cmd):

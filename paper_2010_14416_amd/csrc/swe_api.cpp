@@ -1,6 +1,6 @@
 // C interface (include/swe.h) of the shallow-water step: context, input
 // validation and reordering on the host, device memory, the step loop.
-#include "../../include/swe.h"
+#include "swe.h"
 
 #include <hip/hip_runtime_api.h>
 
@@ -26,7 +26,7 @@ struct DevBufs {
     double *h[2], *hu[2], *hv[2];
     double *z, *man, *gm2, *area, *inr;
     int32_t *internal_of_user, *user_of_internal;
-    int32_t *blk_cell, *blk_edge;
+    int32_t *blk_edge;
     int32_t *be_a, *be_b;
     double *be_nx, *be_ny, *be_len;
     BcEntry *bc;
@@ -120,7 +120,6 @@ size_t layout(const BlockMesh &m, char *base, DevBufs *d)
     t.inr = (double *)take(nc * 8);
     t.internal_of_user = (int32_t *)take(nc * 4);
     t.user_of_internal = (int32_t *)take(nc * 4);
-    t.blk_cell = (int32_t *)take((nb + 1) * 4);
     t.blk_edge = (int32_t *)take((nb + 1) * 4);
     t.be_a = (int32_t *)take(nbe * 4);
     t.be_b = (int32_t *)take(nbe * 4);
@@ -189,8 +188,6 @@ swe_status prepare(swe_ctx *c)
         if ((st = upload(c, d.internal_of_user, m.internal_of_user.data(), nc)))
             return st;
         if ((st = upload(c, d.user_of_internal, m.user_of_internal.data(), nc)))
-            return st;
-        if ((st = upload(c, d.blk_cell, m.blk_cell.data(), m.blk_cell.size())))
             return st;
         if ((st = upload(c, d.blk_edge, m.blk_edge.data(), m.blk_edge.size())))
             return st;
@@ -425,6 +422,7 @@ swe_status swe_set_params(swe_ctx *c, const swe_params *p)
                     "block_threads must be 0, block_cells or 2*block_cells");
     if (p->load_schedule != 0 && p->load_schedule != 1)
         return fail(c, SWE_EINVAL, "load_schedule must be 0 or 1");
+
     if (p->reserved != 0) return fail(c, SWE_EINVAL, "reserved must be 0");
     const bool g_changed = p->g != c->params.g;
     const bool dt_changed = g_changed || p->h_dry != c->params.h_dry;
@@ -667,7 +665,6 @@ swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
     int64_t done = 0;
     const BlockMesh &m = c->mesh;
     swe::StepArgs a{};
-    a.blk_cell = c->d.blk_cell;
     a.blk_edge = c->d.blk_edge;
     a.be_a = c->d.be_a;
     a.be_b = c->d.be_b;
@@ -686,10 +683,12 @@ swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
     a.h_dry = c->params.h_dry;
     a.dt_max = c->params.dt_max;
     a.t_end = t_end;
+    a.n_cells = int32_t(m.n_cells);
     a.n_blocks = m.n_blocks;
     const int threads = c->params.block_threads == 0
                             ? m.block_cells
                             : c->params.block_threads;
+
     auto launch_n = [&](int64_t n) -> swe_status {
         for (int64_t k = 0; k < n; ++k) {
             const int b = c->cur_buf;

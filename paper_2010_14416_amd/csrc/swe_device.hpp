@@ -37,8 +37,7 @@ struct Clock {
 };
 
 struct StepArgs {
-    // mesh (internal order)
-    const int32_t *blk_cell;
+    // mesh (internal order); block b holds cells [b NC, min((b+1) NC, n))
     const int32_t *blk_edge;
     const int32_t *be_a;      // left side of each block edge (coded)
     const int32_t *be_b;      // right side (coded)
@@ -60,6 +59,7 @@ struct StepArgs {
     Clock *clock;
     double *ledger;           // per block: mass added by the positivity fix
     double g, cfl, h_dry, dt_max, t_end;
+    int32_t n_cells;
     int32_t n_blocks;
     int32_t cur;              // clock slot of this step
     long long step_index;
@@ -68,8 +68,8 @@ struct StepArgs {
 // Bytes of dynamic LDS the step kernel needs per block.
 size_t step_lds_bytes(int block_cells);
 
-// schedule 0: edge geometry read only where the edge can carry a flux;
-// 1: edge geometry read with the edge record, before the first barrier.
+// schedule 0: inputs that cannot change the result on dry cells are not
+// read; 1: the geometry of every edge and cell is requested up front.
 hipError_t launch_step(const StepArgs &a, int block_cells, int threads,
                        int schedule, hipStream_t s);
 hipError_t launch_clock_set(Clock *c, double t, long long steps,

@@ -40,16 +40,6 @@ namespace {
 
 constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
 
-__device__ __forceinline__ int xcd_block(int k, int n)
-{
-    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous range of blocks so that halo cells shared by neighbouring
-    // blocks are found in the same L2.
-    const int q = n >> 3, r = n & 7;
-    const int x = k & 7, j = k >> 3;
-    return x * q + min(x, r) + j;
-}
-
 // HLLC flux in the frame of the edge normal (u normal, v tangential).
 // A side at or below h_dry is dry: depth and velocities zero. Wave speeds of
 // eqs. 19-20 with the star depth of eqs. 21-23 (rarefaction estimate clamped
@@ -375,20 +365,48 @@ __device__ __forceinline__ double clock_min_rs(const Clock *c, int slot)
     return m;
 }
 
-// One explicit step for one block of NC consecutive cells, NT threads (NC or
-// 2 NC); threads below NC own a cell, all threads share the block's edges.
-//   phase 1: load the owned cell, the thread's edge record and the state
-//            of that edge's neighbour in another block, all before the
-//            first barrier; stage (h, u, v, z) in LDS;
-//   phase 2: evaluate the edge; its contributions go straight into the LDS
-//            slots [component][side][cell] of the one or two cells of this
-//            block it bounds. An edge between two cells holding no water
-//            (h == 0), or a wall / transmissive edge of such a cell, adds
-//            exact zeros and its geometry is not read (GEOM: read always);
-//   phase 3: each cell sums its three sides in side order, updates, writes
-//            U^{n+1} and R_i / s_i; block reductions; clock.
-// A dry cell whose three sides bring exact zeros needs no area (R/A = R).
-template <int NC, int NT, bool GEOM>
+// Time step of this step: CFL * min R/s of U^n, bounded by dt_max, clipped
+// to t_end (the last step lands on t_end exactly); dt = 0 once t >= t_end.
+struct StepTime {
+    double dt, tn;
+    bool unbounded;
+};
+
+__device__ __forceinline__ StepTime step_time(const StepArgs &a)
+{
+    StepTime st;
+    const double mrs = clock_min_rs(a.clock, a.cur);
+    const double t = a.clock->t[a.cur];
+    st.dt = fmin(a.cfl * mrs, a.dt_max);
+    const double rem = a.t_end - t;
+    if (st.dt >= rem) {
+        st.dt = rem > 0.0 ? rem : 0.0;
+        st.tn = rem > 0.0 ? a.t_end : t;
+    } else {
+        st.tn = t + st.dt;
+    }
+    st.unbounded = !(st.dt < INFINITY);
+    if (st.unbounded) {
+        st.dt = 0.0;
+        st.tn = t;
+    }
+    return st;
+}
+
+// One explicit step, one workgroup per block of NC consecutive cells and NT
+// threads (NC or 2 NC); threads below NC own a cell, all threads share the
+// block's edges (neighbour-block and boundary edges first, so that the
+// first NT of them hold every edge that needs a neighbour's state).
+//
+// Before the first barrier each thread requests its owned cell and its
+// edge records, then the neighbour-block state of its first edge; the cell
+// geometry of wet cells is requested before the second barrier.
+// EAGER: the geometry of every edge and cell is requested with them.
+// Otherwise inputs that cannot change the result are skipped: the geometry
+// of an edge between two cells holding no water is never read, and a dry
+// cell reads its area and inscribed radius only if it receives flux.
+// Both read the same values and round identically.
+template <int NC, int NT, bool EAGER>
 __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
 {
     extern __shared__ double lds[];
@@ -401,73 +419,64 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
     double *s_z = s_v + NC;
     double *s_c = s_z + NC;   // [3 components][3 sides][NC cells]
 
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int c0 = a.blk_cell[blk];
-    const int nc = a.blk_cell[blk + 1] - c0;
+    const int tid = threadIdx.x;
+    const int blk = blockIdx.x;
+    const int c0 = blk * NC;
+    const int nc = min(NC, a.n_cells - c0);
     const int e0 = a.blk_edge[blk];
     const int ne = a.blk_edge[blk + 1] - e0;
-    const int tid = threadIdx.x;
+    const bool owner = tid < NC && tid < nc;
+    const int i = c0 + tid;
     const double g = a.g, h_dry = a.h_dry;
 
-    // ---- phase 1: loads
-    const bool own = tid < NC && tid < nc;
-    const int i = c0 + tid;
+    // phase 1: owned cell, first edge record (+ geometry), neighbour state
     double h = 0.0, hu = 0.0, hv = 0.0, zc = 0.0;
-    if (own) {
+    if (owner) {
         h = a.h0[i];
         hu = a.hu0[i];
         hv = a.hv0[i];
         zc = a.z[i];
     }
-    const bool has_edge = tid < ne;
-    int32_t ea = 0, eb = 0;
+    int32_t ea = 0, eb = 0, ea2 = 0, eb2 = 0;
     double nx = 0.0, ny = 0.0, len = 0.0;
-    if (has_edge) {
+    if (tid < ne) {
         ea = a.be_a[e0 + tid];
         eb = a.be_b[e0 + tid];
-        if (GEOM) {
+        if (EAGER) {
             nx = a.be_nx[e0 + tid];
             ny = a.be_ny[e0 + tid];
             len = a.be_len[e0 + tid];
         }
     }
-    // the edge's neighbour in another block: a side coded as a plain
-    // (non-negative, below kSideBoundary) internal index
+    if (tid + NT < ne) {              // the thread's second edge record
+        ea2 = a.be_a[e0 + tid + NT];
+        eb2 = a.be_b[e0 + tid + NT];
+    }
+    // a side coded as a plain internal index (below kSideBoundary) is a
+    // cell of another block
     CellState X;
-    X.h = 0.0; X.u = 0.0; X.v = 0.0; X.z = 0.0;
-    double xhu = 0.0, xhv = 0.0;
-    const bool xa = uint32_t(ea) < kSideBoundary;
-    const bool xb = uint32_t(eb) < kSideBoundary;
-    const bool need_x = has_edge && (xa || xb);
-    if (need_x) {
-        const int x = xa ? ea : eb;
-        X.h = a.h0[x];
-        xhu = a.hu0[x];
-        xhv = a.hv0[x];
-        X.z = a.z[x];
+    {
+        double xh = 0.0, xhu = 0.0, xhv = 0.0, xz = 0.0;
+        const bool xa = uint32_t(ea) < kSideBoundary;
+        const bool xb = uint32_t(eb) < kSideBoundary;
+        if (tid < ne && (xa || xb)) {
+            const int x = xa ? ea : eb;
+            xh = a.h0[x];
+            xhu = a.hu0[x];
+            xhv = a.hv0[x];
+            xz = a.z[x];
+        }
+        X.h = xh;
+        X.z = xz;
+        X.u = 0.0;
+        X.v = 0.0;
+        if (xh > h_dry) {
+            X.u = xhu / xh;
+            X.v = xhv / xh;
+        }
     }
-
-    // time step of this step: CFL * min R/s of U^n, bounded, clipped to t_end
-    const int cur = a.cur;
-    const int nxt = cur == 2 ? 0 : cur + 1;
-    const double mrs = clock_min_rs(a.clock, cur);
-    const double t = a.clock->t[cur];
-    double dt = fmin(a.cfl * mrs, a.dt_max);
-    const double rem = a.t_end - t;
-    double tn;
-    if (dt >= rem) {
-        dt = rem > 0.0 ? rem : 0.0;
-        tn = rem > 0.0 ? a.t_end : t;
-    } else {
-        tn = t + dt;
-    }
-    const bool unbounded = !(dt < INFINITY);
-    if (unbounded) {
-        dt = 0.0;
-        tn = t;
-    }
-
-    if (own) {
+    const StepTime st = step_time(a);
+    if (owner) {
         s_h[tid] = h;
         s_z[tid] = zc;
         if (h > h_dry) {
@@ -478,60 +487,68 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
             s_v[tid] = 0.0;
         }
     }
-    if (need_x && X.h > h_dry) {
-        X.u = xhu / X.h;
-        X.v = xhv / X.h;
-    }
     __syncthreads();
 
-    // ---- phase 2: edges
+    // phase 2: every edge of the block once. Contributions go straight into
+    // the LDS slots [component][side][cell] of the one or two cells of the
+    // block the edge bounds. An edge between two cells holding no water
+    // (h == 0), or a wall / transmissive edge of such a cell, adds exact
+    // zeros.
     for (int k = tid; k < ne; k += NT) {
-        Side pa = decode_side(ea), pb = decode_side(eb);
+        int32_t va = ea, vb = eb;
+        double enx = nx, eny = ny, elen = len;
         CellState Y = X;
-        double qx = nx, qy = ny, ql = len;
-        if (k != tid) {               // blocks with more than NT edges
-            pa = decode_side(a.be_a[e0 + k]);
-            pb = decode_side(a.be_b[e0 + k]);
+        if (k == tid + NT) {
+            va = ea2;
+            vb = eb2;
+        } else if (k != tid) {        // blocks with more than 2 NT edges
+            va = a.be_a[e0 + k];
+            vb = a.be_b[e0 + k];
+        }
+        if (k != tid) {
+            if (EAGER) {
+                enx = a.be_nx[e0 + k];
+                eny = a.be_ny[e0 + k];
+                elen = a.be_len[e0 + k];
+            }
+        }
+        const Side pa = decode_side(va), pb = decode_side(vb);
+        if (k != tid) {
             if (pa.kind == 1) Y = load_cell(a, pa.global);
             if (pb.kind == 1) Y = load_cell(a, pb.global);
-            if (GEOM) {
-                qx = a.be_nx[e0 + k];
-                qy = a.be_ny[e0 + k];
-                ql = a.be_len[e0 + k];
-            }
         }
-        CellState L, R;
-        R.h = 0.0; R.u = 0.0; R.v = 0.0; R.z = 0.0;
+        CellState Lc, Rc;
+        Rc.h = 0.0; Rc.u = 0.0; Rc.v = 0.0; Rc.z = 0.0;
         if (pa.kind == 0) {
-            L.h = s_h[pa.local]; L.u = s_u[pa.local];
-            L.v = s_v[pa.local]; L.z = s_z[pa.local];
+            Lc.h = s_h[pa.local]; Lc.u = s_u[pa.local];
+            Lc.v = s_v[pa.local]; Lc.z = s_z[pa.local];
         } else {
-            L = Y;
+            Lc = Y;
         }
         bool idle;
-        BcEntry pbc{};
+        BcEntry bc{};
         if (pb.kind == 2) {
-            pbc = a.bc[pb.global];
-            idle = L.h == 0.0 && (pbc.kind == 0 || pbc.kind == 1);
+            bc = a.bc[pb.global];
+            idle = Lc.h == 0.0 && (bc.kind == 0 || bc.kind == 1);
         } else {
             if (pb.kind == 0) {
-                R.h = s_h[pb.local]; R.u = s_u[pb.local];
-                R.v = s_v[pb.local]; R.z = s_z[pb.local];
+                Rc.h = s_h[pb.local]; Rc.u = s_u[pb.local];
+                Rc.v = s_v[pb.local]; Rc.z = s_z[pb.local];
             } else {
-                R = Y;
+                Rc = Y;
             }
-            idle = L.h == 0.0 && R.h == 0.0;
+            idle = Lc.h == 0.0 && Rc.h == 0.0;
         }
         double cl0 = 0.0, cl1 = 0.0, cl2 = 0.0;
         double cr0 = 0.0, cr1 = 0.0, cr2 = 0.0;
         if (!idle) {
-            if (!GEOM) {
-                qx = a.be_nx[e0 + k];
-                qy = a.be_ny[e0 + k];
-                ql = a.be_len[e0 + k];
+            if (!EAGER) {
+                enx = a.be_nx[e0 + k];
+                eny = a.be_ny[e0 + k];
+                elen = a.be_len[e0 + k];
             }
-            edge_contrib(g, h_dry, pb.kind == 2, pbc, L, R, qx, qy, ql, cl0,
-                         cl1, cl2, cr0, cr1, cr2);
+            edge_contrib(g, h_dry, pb.kind == 2, bc, Lc, Rc, enx, eny, elen,
+                         cl0, cl1, cl2, cr0, cr1, cr2);
         }
         if (pa.kind == 0) {
             double *d = s_c + pa.k * NC + pa.local;
@@ -546,12 +563,23 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
             d[6 * NC] = cr2;
         }
     }
+    // cell geometry: every cell (EAGER), else the wet ones, which always
+    // need it; a dry cell requests its own in phase 3 if it receives flux
+    double area = 0.0, gm2 = 0.0, inr = 0.0;
+    if (owner && (EAGER || h > h_dry)) {
+        area = a.area[i];
+        gm2 = a.gm2[i];
+        inr = a.inradius[i];
+    }
     __syncthreads();
 
-    // ---- phase 3: cells
+    // phase 3: each owned cell sums its three sides in side order, updates
+    // and writes U^{n+1}; R_i/s_i, the clamped mass and the non-finite flag
+    // go to the block reduction. A dry cell whose three sides bring exact
+    // zeros needs no area (R/A = R exactly).
     double rs = INFINITY, clamp = 0.0;
     unsigned bad = 0;
-    if (own) {
+    if (owner) {
         double R0 = 0.0, R1 = 0.0, R2 = 0.0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -560,18 +588,20 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
             R2 += s_c[(6 + k) * NC + tid];
         }
         double hn = h, hun = hu, hvn = hv;
+        const double dt = st.dt;
         if (dt > 0.0) {
             if (h <= h_dry && R0 == 0.0 && R1 == 0.0 && R2 == 0.0) {
-                // R/A = R exactly; no friction below h_dry; h + dt*(+-0)
-                // cannot go negative
+                // no friction below h_dry; h + dt*(+-0) cannot go negative
                 hn = h + dt * R0;
                 hun = 0.0;
                 hvn = 0.0;
             } else {
-                const double A = a.area[i];
-                const double gm2 = h > h_dry ? a.gm2[i] : 0.0;
-                cell_update(h_dry, dt, A, gm2, h, hu, hv, R0, R1, R2, hn,
-                            hun, hvn, clamp);
+                if (!EAGER && h <= h_dry) {
+                    area = a.area[i];
+                    inr = a.inradius[i];
+                }
+                cell_update(h_dry, dt, area, h > h_dry ? gm2 : 0.0, h, hu, hv,
+                            R0, R1, R2, hn, hun, hvn, clamp);
             }
         }
         a.h1[i] = hn;
@@ -579,13 +609,12 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
         a.hv1[i] = hvn;
         if (!isfinite(hn) || !isfinite(hun) || !isfinite(hvn)) bad = 1u;
         if (hn > h_dry) {
-            const double inr = a.inradius[i];
             const double u = hun / hn, v = hvn / hn;
             rs = inr / (sqrt(g * hn) + sqrt(u * u + v * v));
         }
     }
-    block_finish<NT>(a, blk, rs, clamp, bad, unbounded, dt, tn, nxt,
-                     red_min, red_sum, red_bad);
+    block_finish<NT>(a, blk, rs, clamp, bad, st.unbounded, st.dt, st.tn,
+                     a.cur == 2 ? 0 : a.cur + 1, red_min, red_sum, red_bad);
 }
 
 __global__ void clock_set_kernel(Clock *c, double t, long long steps)
@@ -770,13 +799,12 @@ namespace {
 template <int NC, int NT>
 void launch_one(const StepArgs &a, int schedule, hipStream_t s)
 {
-    const size_t lds = step_lds_bytes(NC);
     if (schedule == 0)
         hipLaunchKernelGGL((swe_step_kernel<NC, NT, false>), dim3(a.n_blocks),
-                           dim3(NT), lds, s, a);
+                           dim3(NT), step_lds_bytes(NC), s, a);
     else
         hipLaunchKernelGGL((swe_step_kernel<NC, NT, true>), dim3(a.n_blocks),
-                           dim3(NT), lds, s, a);
+                           dim3(NT), step_lds_bytes(NC), s, a);
 }
 }  // namespace
 

@@ -402,9 +402,11 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
     for (int64_t i = 0; i < nc; ++i) M.total_area += M.area[i];
 
     // ---- blocks of block_cells consecutive internal cells and their edges:
-    //      edges with both cells in the block first, then edges to another
-    //      block, then boundary edges; each group in order of first use (an
-    //      edge inside the block is first used by its lower-numbered cell).
+    //      edges to another block first (the step kernel prefetches the
+    //      neighbour state of the first block_cells edges), then boundary
+    //      edges, then edges with both cells in the block; each group in
+    //      order of first use (an edge inside the block is first used by its
+    //      lower-numbered cell).
     //      Each side of a block edge is encoded as
     //        in the block:  kSideLocal | k << 12 | local cell   (k = the
     //                       cell's side along this edge, 0..2)
@@ -470,9 +472,9 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
                 for (int k = 0; k < 3; ++k) {
                     const int64_t j = side_nb[3 * i + k];
                     const Use use{i, k, side_e[3 * i + k]};
-                    if (j < 0) grp[2].push_back(use);
-                    else if (j < c0 || j >= c1) grp[1].push_back(use);
-                    else if (i < j) grp[0].push_back(use);
+                    if (j < 0) grp[1].push_back(use);
+                    else if (j < c0 || j >= c1) grp[0].push_back(use);
+                    else if (i < j) grp[2].push_back(use);
                 }
             // side code of internal cell j in this block along edge e
             auto local_code = [&](int64_t j, int32_t e) {

@@ -99,7 +99,8 @@ def test_lake_at_rest_gpu():
 @pytest.mark.parametrize("block_cells,reorder,threads,schedule", [
     (64, True, 0, 0), (128, True, 0, 0), (512, True, 0, 0),
     (256, False, 0, 0), (256, True, 512, 0), (64, True, 128, 0),
-    (512, True, 1024, 0), (256, True, 0, 1), (128, True, 256, 1)])
+    (512, True, 1024, 0), (256, True, 0, 1), (128, True, 256, 1),
+    (64, True, 0, 1)])
 def test_blocking_and_order_do_not_change_bits(block_cells, reorder,
                                                threads, schedule):
     """Per-cell arithmetic is independent of how cells are grouped into
