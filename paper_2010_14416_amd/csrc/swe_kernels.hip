@@ -428,6 +428,7 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
     const bool owner = tid < NC && tid < nc;
     const int i = c0 + tid;
     const double g = a.g, h_dry = a.h_dry;
+    const StepTime st = step_time(a);
 
     // phase 1: owned cell, first edge record (+ geometry), neighbour state
     double h = 0.0, hu = 0.0, hv = 0.0, zc = 0.0;
@@ -475,7 +476,6 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
             X.v = xhv / xh;
         }
     }
-    const StepTime st = step_time(a);
     if (owner) {
         s_h[tid] = h;
         s_z[tid] = zc;
@@ -494,29 +494,11 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
     // block the edge bounds. An edge between two cells holding no water
     // (h == 0), or a wall / transmissive edge of such a cell, adds exact
     // zeros.
-    for (int k = tid; k < ne; k += NT) {
-        int32_t va = ea, vb = eb;
-        double enx = nx, eny = ny, elen = len;
-        CellState Y = X;
-        if (k == tid + NT) {
-            va = ea2;
-            vb = eb2;
-        } else if (k != tid) {        // blocks with more than 2 NT edges
-            va = a.be_a[e0 + k];
-            vb = a.be_b[e0 + k];
-        }
-        if (k != tid) {
-            if (EAGER) {
-                enx = a.be_nx[e0 + k];
-                eny = a.be_ny[e0 + k];
-                elen = a.be_len[e0 + k];
-            }
-        }
+    // one edge: its record (va, vb), the state Y of a side in another
+    // block, the geometry (if already loaded)
+    auto edge = [&](int k, int32_t va, int32_t vb, const CellState &Y,
+                    double enx, double eny, double elen) {
         const Side pa = decode_side(va), pb = decode_side(vb);
-        if (k != tid) {
-            if (pa.kind == 1) Y = load_cell(a, pa.global);
-            if (pb.kind == 1) Y = load_cell(a, pb.global);
-        }
         CellState Lc, Rc;
         Rc.h = 0.0; Rc.u = 0.0; Rc.v = 0.0; Rc.z = 0.0;
         if (pa.kind == 0) {
@@ -562,11 +544,31 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
             d[3 * NC] = cr1;
             d[6 * NC] = cr2;
         }
+    };
+    if (tid < ne) edge(tid, ea, eb, X, nx, ny, len);
+    for (int k = tid + NT; k < ne; k += NT) {   // blocks with > NT edges
+        int32_t va = ea2, vb = eb2;
+        if (k != tid + NT) {
+            va = a.be_a[e0 + k];
+            vb = a.be_b[e0 + k];
+        }
+        double enx = 0.0, eny = 0.0, elen = 0.0;
+        if (EAGER) {
+            enx = a.be_nx[e0 + k];
+            eny = a.be_ny[e0 + k];
+            elen = a.be_len[e0 + k];
+        }
+        CellState Y;
+        Y.h = 0.0; Y.u = 0.0; Y.v = 0.0; Y.z = 0.0;
+        if (uint32_t(va) < kSideBoundary) Y = load_cell(a, va);
+        if (uint32_t(vb) < kSideBoundary) Y = load_cell(a, vb);
+        edge(k, va, vb, Y, enx, eny, elen);
     }
     // cell geometry: every cell (EAGER), else the wet ones, which always
     // need it; a dry cell requests its own in phase 3 if it receives flux
     double area = 0.0, gm2 = 0.0, inr = 0.0;
-    if (owner && (EAGER || h > h_dry)) {
+    const double hc = owner ? s_h[tid] : 0.0;   // h of the owned cell
+    if (owner && (EAGER || hc > h_dry)) {
         area = a.area[i];
         gm2 = a.gm2[i];
         inr = a.inradius[i];
@@ -587,21 +589,21 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
             R1 += s_c[(3 + k) * NC + tid];
             R2 += s_c[(6 + k) * NC + tid];
         }
-        double hn = h, hun = hu, hvn = hv;
+        double hn = hc, hun = hu, hvn = hv;
         const double dt = st.dt;
         if (dt > 0.0) {
-            if (h <= h_dry && R0 == 0.0 && R1 == 0.0 && R2 == 0.0) {
+            if (hc <= h_dry && R0 == 0.0 && R1 == 0.0 && R2 == 0.0) {
                 // no friction below h_dry; h + dt*(+-0) cannot go negative
-                hn = h + dt * R0;
+                hn = hc + dt * R0;
                 hun = 0.0;
                 hvn = 0.0;
             } else {
-                if (!EAGER && h <= h_dry) {
+                if (!EAGER && hc <= h_dry) {
                     area = a.area[i];
                     inr = a.inradius[i];
                 }
-                cell_update(h_dry, dt, area, h > h_dry ? gm2 : 0.0, h, hu, hv,
-                            R0, R1, R2, hn, hun, hvn, clamp);
+                cell_update(h_dry, dt, area, hc > h_dry ? gm2 : 0.0, hc, hu,
+                            hv, R0, R1, R2, hn, hun, hvn, clamp);
             }
         }
         a.h1[i] = hn;
