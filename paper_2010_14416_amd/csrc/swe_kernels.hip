@@ -355,16 +355,6 @@ __device__ __forceinline__ Side decode_side(int32_t v)
     return s;
 }
 
-// Minimum of R/s over the XCD slots of one clock slot.
-__device__ __forceinline__ double clock_min_rs(const Clock *c, int slot)
-{
-    double m = __longlong_as_double((long long)c->minrs[slot][0][0]);
-#pragma unroll
-    for (int x = 1; x < kClockLanes; ++x)
-        m = fmin(m, __longlong_as_double((long long)c->minrs[slot][x][0]));
-    return m;
-}
-
 // Time step of this step: CFL * min R/s of U^n, bounded by dt_max, clipped
 // to t_end (the last step lands on t_end exactly); dt = 0 once t >= t_end.
 struct StepTime {
@@ -372,11 +362,34 @@ struct StepTime {
     bool unbounded;
 };
 
-__device__ __forceinline__ StepTime step_time(const StepArgs &a)
+// Clock words of this step, read with one vector load per lane so that they
+// travel with the block's first loads: lane x < kClockLanes holds lane x of
+// the time-step minimum, lane kClockLanes the time t.
+__device__ __forceinline__ double clock_word(const StepArgs &a)
+{
+    const int lane = int(threadIdx.x & 63u);
+    const Clock *c = a.clock;
+    if (lane < kClockLanes)
+        return __longlong_as_double((long long)c->minrs[a.cur][lane][0]);
+    if (lane == kClockLanes) return c->t[a.cur];
+    return 0.0;
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(b), lane));
+    const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(b >> 32), lane));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ StepTime step_time(const StepArgs &a, double word)
 {
     StepTime st;
-    const double mrs = clock_min_rs(a.clock, a.cur);
-    const double t = a.clock->t[a.cur];
+    double mrs = read_lane(word, 0);
+#pragma unroll
+    for (int x = 1; x < kClockLanes; ++x) mrs = fmin(mrs, read_lane(word, x));
+    const double t = read_lane(word, kClockLanes);
     st.dt = fmin(a.cfl * mrs, a.dt_max);
     const double rem = a.t_end - t;
     if (st.dt >= rem) {
@@ -428,7 +441,6 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
     const bool owner = tid < NC && tid < nc;
     const int i = c0 + tid;
     const double g = a.g, h_dry = a.h_dry;
-    const StepTime st = step_time(a);
 
     // phase 1: owned cell, first edge record (+ geometry), neighbour state
     double h = 0.0, hu = 0.0, hv = 0.0, zc = 0.0;
@@ -438,6 +450,7 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
         hv = a.hv0[i];
         zc = a.z[i];
     }
+    const double cw = clock_word(a);
     int32_t ea = 0, eb = 0, ea2 = 0, eb2 = 0;
     double nx = 0.0, ny = 0.0, len = 0.0;
     if (tid < ne) {
@@ -476,6 +489,7 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
             X.v = xhv / xh;
         }
     }
+    const StepTime st = step_time(a, cw);
     if (owner) {
         s_h[tid] = h;
         s_z[tid] = zc;
