@@ -32,6 +32,7 @@ struct DevBufs {
     BcEntry *bc;
     Clock *clock;
     double *ledger;
+    int32_t *quiet;
     double *part_mass;
     unsigned long long *part_wet;
     unsigned *flag;
@@ -70,6 +71,7 @@ struct swe_ctx {
     double last_dt_host = 0.0;
     long long step_index = 0;  // steps launched since the mesh was set
     bool uploaded = false;     // host memory queued on the stream
+    bool quiet_dirty = true;   // state buffers written outside a step
 };
 
 namespace {
@@ -129,6 +131,7 @@ size_t layout(const BlockMesh &m, char *base, DevBufs *d)
     t.bc = (BcEntry *)take(sizeof(BcEntry) * SWE_MAX_TAG);
     t.clock = (Clock *)take(sizeof(Clock));
     t.ledger = (double *)take(nb * 8);
+    t.quiet = (int32_t *)take(nb * 4);
     t.part_mass = (double *)take(kDiagParts * 8);
     t.part_wet = (unsigned long long *)take(kDiagParts * 8);
     t.flag = (unsigned *)take(256);
@@ -225,6 +228,13 @@ swe_status prepare(swe_ctx *c)
         if ((st = upload(c, d.hv[c->cur_buf], c->hv.data(), nc))) return st;
         c->state_dirty = false;
         c->dt_valid = false;
+        c->quiet_dirty = true;
+    }
+    if (c->quiet_dirty) {
+        // the step kernel may skip stores only after two steps from here
+        HIPCHK(c, swe::launch_fill_u32((unsigned *)d.quiet, 0u, m.n_blocks,
+                                       c->stream));
+        c->quiet_dirty = false;
     }
     if (c->bc_dirty) {
         // inflow discharge per unit length of each tag
@@ -586,6 +596,7 @@ swe_status swe_set_state(swe_ctx *c, const double *h, const double *hu,
                                   c->d.hv[b], c->d.user_of_internal, nc,
                                   c->stream));
     c->dt_valid = false;
+    c->quiet_dirty = true;
     return prepare(c);
 }
 
@@ -678,6 +689,7 @@ swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
     a.bc = c->d.bc;
     a.clock = c->d.clock;
     a.ledger = c->d.ledger;
+    a.quiet = c->d.quiet;
     a.g = c->params.g;
     a.cfl = c->params.cfl;
     a.h_dry = c->params.h_dry;

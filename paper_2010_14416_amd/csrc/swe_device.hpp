@@ -58,6 +58,8 @@ struct StepArgs {
     double *hv1;
     Clock *clock;
     double *ledger;           // per block: mass added by the positivity fix
+    int32_t *quiet;           // per block: consecutive steps (capped at 2) in
+                              // which every cell took the quiet dry path
     double g, cfl, h_dry, dt_max, t_end;
     int32_t n_cells;
     int32_t n_blocks;

@@ -281,7 +281,8 @@ __device__ __forceinline__ double wave_sum(double v)
 template <int NT>
 __device__ __forceinline__ void block_finish(const StepArgs &a, int blk,
                                              double rs, double clamp,
-                                             unsigned bad, bool unbounded,
+                                             unsigned bad, bool active,
+                                             int quiet_steps, bool unbounded,
                                              double dt, double tn, int nxt,
                                              double *red_min, double *red_sum,
                                              unsigned *red_bad)
@@ -290,21 +291,25 @@ __device__ __forceinline__ void block_finish(const StepArgs &a, int blk,
     rs = wave_min(rs);
     clamp = wave_sum(clamp);
     const unsigned long long ballot = __ballot(bad != 0u);
+    const unsigned long long busy = __ballot(active);
     const int wave = tid >> 6, lane = tid & 63;
     if (lane == 0) {
         red_min[wave] = rs;
         red_sum[wave] = clamp;
-        red_bad[wave] = ballot != 0ull ? 1u : 0u;
+        red_bad[wave] = (ballot != 0ull ? 1u : 0u) | (busy != 0ull ? 2u : 0u);
     }
     __syncthreads();
     if (tid == 0) {
         double m = red_min[0], cs = red_sum[0];
-        unsigned anybad = red_bad[0];
+        unsigned flags = red_bad[0];
         for (int w = 1; w < NT / 64; ++w) {
             m = fmin(m, red_min[w]);
             cs += red_sum[w];
-            anybad |= red_bad[w];
+            flags |= red_bad[w];
         }
+        const bool anybad = (flags & 1u) != 0u;
+        const int q = (flags & 2u) ? 0 : min(quiet_steps + 1, 2);
+        if (q != quiet_steps) a.quiet[blk] = q;
         if (m < INFINITY)
             atomicMin(&a.clock->minrs[nxt][blockIdx.x & (kClockLanes - 1)][0],
                       (unsigned long long)__double_as_longlong(m));
@@ -406,6 +411,22 @@ __device__ __forceinline__ StepTime step_time(const StepArgs &a, double word)
     return st;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2. Workgroup w runs block xcd_block(w): runs of kXcdChunk consecutive
+// blocks (neighbours along the space-filling curve, which share halo cells)
+// go to one XCD, and the runs are dealt round-robin so that every XCD gets
+// a similar mix of wet and dry blocks. Blocks past the last whole round of
+// 8 kXcdChunk keep their own index.
+constexpr int kXcdChunk = 4;
+
+__device__ __forceinline__ int xcd_block(int w, int n_blocks)
+{
+    constexpr int R = 8 * kXcdChunk;
+    if (w >= (n_blocks / R) * R) return w;
+    const int x = w & 7, j = w >> 3;
+    return (j / kXcdChunk) * R + x * kXcdChunk + j % kXcdChunk;
+}
+
 // One explicit step, one workgroup per block of NC consecutive cells and NT
 // threads (NC or 2 NC); threads below NC own a cell, all threads share the
 // block's edges (neighbour-block and boundary edges first, so that the
@@ -433,7 +454,7 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
     double *s_c = s_z + NC;   // [3 components][3 sides][NC cells]
 
     const int tid = threadIdx.x;
-    const int blk = blockIdx.x;
+    const int blk = xcd_block(blockIdx.x, a.n_blocks);
     const int c0 = blk * NC;
     const int nc = min(NC, a.n_cells - c0);
     const int e0 = a.blk_edge[blk];
@@ -443,11 +464,10 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
     const double g = a.g, h_dry = a.h_dry;
 
     // phase 1: owned cell, first edge record (+ geometry), neighbour state
+    const int quiet_steps = a.quiet[blk];
     double h = 0.0, hu = 0.0, hv = 0.0, zc = 0.0;
     if (owner) {
         h = a.h0[i];
-        hu = a.hu0[i];
-        hv = a.hv0[i];
         zc = a.z[i];
     }
     const double cw = clock_word(a);
@@ -465,6 +485,11 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
     if (tid + NT < ne) {              // the thread's second edge record
         ea2 = a.be_a[e0 + tid + NT];
         eb2 = a.be_b[e0 + tid + NT];
+    }
+    // the momentum of a dry cell is read in phase 3, and only if needed
+    if (owner && h > h_dry) {
+        hu = a.hu0[i];
+        hv = a.hv0[i];
     }
     // a side coded as a plain internal index (below kSideBoundary) is a
     // cell of another block
@@ -595,6 +620,7 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
     // zeros needs no area (R/A = R exactly).
     double rs = INFINITY, clamp = 0.0;
     unsigned bad = 0;
+    bool active = owner;   // owned cell not on the quiet dry path
     if (owner) {
         double R0 = 0.0, R1 = 0.0, R2 = 0.0;
 #pragma unroll
@@ -605,31 +631,42 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
         }
         double hn = hc, hun = hu, hvn = hv;
         const double dt = st.dt;
-        if (dt > 0.0) {
-            if (hc <= h_dry && R0 == 0.0 && R1 == 0.0 && R2 == 0.0) {
-                // no friction below h_dry; h + dt*(+-0) cannot go negative
-                hn = hc + dt * R0;
-                hun = 0.0;
-                hvn = 0.0;
-            } else {
-                if (!EAGER && hc <= h_dry) {
+        if (dt > 0.0 && hc <= h_dry && R0 == 0.0 && R1 == 0.0 && R2 == 0.0) {
+            // no friction below h_dry; h + dt*(+-0) cannot go negative
+            hn = hc + dt * R0;
+            hun = 0.0;
+            hvn = 0.0;
+            active = false;
+        } else {
+            if (hc <= h_dry) {
+                hu = a.hu0[i];
+                hv = a.hv0[i];
+                if (!EAGER) {
                     area = a.area[i];
                     inr = a.inradius[i];
                 }
+            }
+            hun = hu;
+            hvn = hv;
+            if (dt > 0.0)
                 cell_update(h_dry, dt, area, hc > h_dry ? gm2 : 0.0, hc, hu,
                             hv, R0, R1, R2, hn, hun, hvn, clamp);
-            }
         }
-        a.h1[i] = hn;
-        a.hu1[i] = hun;
-        a.hv1[i] = hvn;
+        // a quiet cell of a block quiet in the two previous steps already
+        // holds (h, 0, 0) in the output buffer (it held U^{n-1} = U^n)
+        if (active || quiet_steps < 2) {
+            a.h1[i] = hn;
+            a.hu1[i] = hun;
+            a.hv1[i] = hvn;
+        }
         if (!isfinite(hn) || !isfinite(hun) || !isfinite(hvn)) bad = 1u;
         if (hn > h_dry) {
             const double u = hun / hn, v = hvn / hn;
             rs = inr / (sqrt(g * hn) + sqrt(u * u + v * v));
         }
     }
-    block_finish<NT>(a, blk, rs, clamp, bad, st.unbounded, st.dt, st.tn,
+    block_finish<NT>(a, blk, rs, clamp, bad, active, quiet_steps,
+                     st.unbounded, st.dt, st.tn,
                      a.cur == 2 ? 0 : a.cur + 1, red_min, red_sum, red_bad);
 }
 
