@@ -19,6 +19,7 @@ kernel runs on) and the FP64 CPU oracle timed on a bounded sample.
 import argparse
 import hashlib
 import json
+import re
 import math
 import os
 import sys
@@ -188,9 +189,10 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=2048,
                     help="size of the reference copy (0: skip)")
     ap.add_argument("--sweep", default="",
-                    help="comma list of CELLSxTHREADS[sSCHEDULE] block shapes "
-                         "to time on the same mesh before the main run "
-                         "(stderr), e.g. 256x512,256x512s1")
+                    help="comma list of CELLSxTHREADS[sSCHEDULE][mMONITORS]"
+                         "[aSTORE_ALL] variants to time on the same mesh "
+                         "before the main run (stderr), e.g. "
+                         "256x256,256x256s1,256x256m1,256x256a1")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV",
                                                         "WRITE_CSV"),
                     help="write the step kernel's traffic summary from two "
@@ -219,13 +221,15 @@ def main():
     log(f"workload {case.name}: {case.n_cells} cells "
         f"({time.perf_counter() - t0:.1f} s to generate)")
     for shape in filter(None, args.sweep.split(",")):
-        sched = 0
-        if "s" in shape:
-            shape, sched = shape.split("s")
-            sched = int(sched)
-        bc, bt = (int(x) for x in shape.lower().split("x"))
+        m = re.fullmatch(r"(\d+)x(\d+)(?:s(\d))?(?:m(\d))?(?:a(\d))?",
+                         shape.lower())
+        if not m:
+            raise SystemExit(f"bad sweep entry {shape!r}")
+        bc, bt = int(m.group(1)), int(m.group(2))
+        sched, mon, sall = (int(m.group(k) or 0) for k in (3, 4, 5))
         sw = Solver(case, device=0, block_cells=bc,
-                    params={"block_threads": bt, "load_schedule": sched})
+                    params={"block_threads": bt, "load_schedule": sched,
+                            "monitors": mon, "store_all": sall})
         sw.advance(args.warmup + 1, want_time=True)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -236,7 +240,8 @@ def main():
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
         sw.time()
-        log(f"sweep {bc}x{bt} schedule {sched}: {ms:.4f} ms/step, "
+        log(f"sweep {bc}x{bt} schedule {sched} monitors {mon} store_all "
+            f"{sall}: {ms:.4f} ms/step, "
             f"{case.n_cells / (ms * 1e-3):.4e} cell-updates/s, "
             f"{ALG_BYTES_PER_CELL * case.n_cells / (ms * 1e-3) / 1e9:.0f} "
             f"GB/s algorithmic")

@@ -85,6 +85,16 @@ typedef struct {
                               holding no water) (default); 1: all geometry
                               requested with the state, before the first
                               barrier. Same results; a tuning switch          */
+    int32_t monitors;      /* 1: every step also updates the discharge
+                              monitors and the flood envelope (see
+                              swe_get_discharge, swe_get_envelope); 0: off
+                              (0). Turning it on resets them                 */
+    int32_t store_all;     /* 1: every cell stores U^{n+1} every step;
+                              0: a cell left unchanged on the quiet dry path
+                              (h <= h_dry, no flux) in a block that was quiet
+                              for the two previous steps skips its store,
+                              since the output buffer already holds the same
+                              values (0). Same results; a tuning switch      */
     int32_t reserved;      /* must be 0                                       */
 } swe_params;
 
@@ -200,6 +210,33 @@ swe_status swe_advance(swe_ctx *ctx, int64_t max_steps, double t_end,
  * with h > h_dry. Synchronises the stream. */
 swe_status swe_get_diagnostics(swe_ctx *ctx, double *mass, double *ledger,
                                int64_t *n_wet);
+
+/* Discharge monitors and flood envelope (swe_params.monitors = 1), the
+ * outflow and inflow rates of a river reach and the maximum-depth map from
+ * which flood lines are drawn (sec. 5). Both are reset to the current state
+ * when monitors are turned on, when the state is set and by
+ * swe_reset_monitors().
+ *
+ * swe_get_discharge: for boundary tag `tag`, *rate = the volume leaving the
+ * domain per unit time through the tag's edges during the last step,
+ * sum of L_e G_1 over the edges (G_1 = the normal mass flux of the edge's
+ * boundary flux, outward positive; an inflow tag gives -Q) [m^3/s], and
+ * *volume = sum over steps of dt times that rate since the last reset [m^3].
+ * With the positivity ledger they close the water balance:
+ *   mass(t) - mass(t_reset) = -(sum of volumes over tags) + ledger change.
+ * Either pointer may be NULL. Synchronises the stream.
+ *
+ * swe_get_envelope: per cell (user order) the highest depth h reached since
+ * the reset (the reset state included) and the first simulated time at the
+ * end of a step with h > h_dry (the reset time for cells wet at the reset,
+ * +INFINITY for cells never wet). Synchronises the stream.
+ *
+ * Both return SWE_ENOTREADY while monitors are off. */
+swe_status swe_reset_monitors(swe_ctx *ctx);
+swe_status swe_get_discharge(swe_ctx *ctx, int32_t tag, double *rate,
+                             double *volume);
+swe_status swe_get_envelope(swe_ctx *ctx, double *h_max, double *t_wet,
+                            swe_mem mem);
 
 /* Device memory: by default the library allocates it on first use. A
  * caller that owns device memory (e.g. a torch uint8 tensor) can instead

@@ -82,6 +82,9 @@ def lib():
         L.ora_mass.restype = _d
         L.ora_mass.argtypes = [_p]
         L.ora_run.argtypes = [_p, _i64, _d, _i, _pi64, _pd]
+        L.ora_reset_monitors.argtypes = [_p]
+        L.ora_discharge.argtypes = [_p, _i, _pd, _pd]
+        L.ora_envelope.argtypes = [_p, _pd, _pd]
         L.ora_error.restype = C.c_char_p
         L.ora_error.argtypes = [_p]
         L.ora_star_depth.argtypes = [_d, _d, _d, _d, _d, _pd, _pd,
@@ -250,6 +253,23 @@ class Oracle:
                            C.byref(ledger))
         return dict(t=t.value, last_dt=dt.value, step=step.value,
                     ledger=ledger.value)
+
+    def reset_monitors(self):
+        lib().ora_reset_monitors(self._h)
+
+    def discharge(self, tag: int):
+        """(rate of the last step, volume since the reset) leaving through
+        boundary tag `tag`."""
+        r, v = C.c_double(), C.c_double()
+        lib().ora_discharge(self._h, int(tag), C.byref(r), C.byref(v))
+        return r.value, v.value
+
+    def envelope(self):
+        n = self.n_cells
+        hmax, twet = np.empty(n), np.empty(n)
+        lib().ora_envelope(self._h, _ptr(hmax, C.c_double),
+                           _ptr(twet, C.c_double))
+        return hmax, twet
 
     def min_rs(self) -> float:
         return lib().ora_min_rs(self._h)

@@ -63,6 +63,10 @@ typedef struct ora {
     double *z, *man, *h, *hu, *hv;
     double *cl, *cr;              /* 3*ne contributions to left / right cell */
     double *clamp;                /* per cell, mass added by positivity */
+    /* monitors: per edge (boundary edges only) the outward volume rate of
+       the last step and the volume since the reset; per cell the highest
+       depth and the first time with h > h_dry (INFINITY: never) */
+    double *brate, *bvol, *hmax, *twet;
     ora_bc bc[ORA_MAX_TAG];
     double g, cfl, h_dry, dt_max;
     double t, last_dt, ledger;
@@ -392,6 +396,7 @@ void ora_destroy(ora *o)
     free(o->c_edge); free(o->c_right);
     free(o->z); free(o->man); free(o->h); free(o->hu); free(o->hv);
     free(o->cl); free(o->cr); free(o->clamp);
+    free(o->brate); free(o->bvol); free(o->hmax); free(o->twet);
     free(o);
 }
 
@@ -562,9 +567,14 @@ ora *ora_create(int64_t nn, const double *xy, int64_t nc, const int32_t *tri,
     o->cl = malloc(3 * ne * sizeof(double));
     o->cr = malloc(3 * ne * sizeof(double));
     o->clamp = malloc(nc * sizeof(double));
+    o->brate = calloc(ne, sizeof(double));
+    o->bvol = calloc(ne, sizeof(double));
+    o->hmax = calloc(nc, sizeof(double));
+    o->twet = malloc(nc * sizeof(double));
     if (!o->z || !o->man || !o->h || !o->hu || !o->hv || !o->cl || !o->cr ||
-        !o->clamp)
+        !o->clamp || !o->brate || !o->bvol || !o->hmax || !o->twet)
         FAIL("out of memory");
+    for (int64_t i = 0; i < nc; ++i) o->twet[i] = INFINITY;
     for (int k = 0; k < ORA_MAX_TAG; ++k) o->bc[k].kind = K_WALL;
     o->g = 9.81; o->cfl = 0.9; o->h_dry = 1e-6; o->dt_max = INFINITY;
     return o;
@@ -604,6 +614,8 @@ int ora_set_fields(ora *o, const double *z, const double *man)
     return 0;
 }
 
+void ora_reset_monitors(ora *o);
+
 int ora_set_state(ora *o, const double *h, const double *hu, const double *hv)
 {
     for (int64_t i = 0; i < o->nc; ++i)
@@ -613,7 +625,41 @@ int ora_set_state(ora *o, const double *h, const double *hu, const double *hv)
     memcpy(o->h, h, o->nc * sizeof(double));
     memcpy(o->hu, hu, o->nc * sizeof(double));
     memcpy(o->hv, hv, o->nc * sizeof(double));
+    ora_reset_monitors(o);
     return 0;
+}
+
+/* Monitors of the outflow / inflow rates (sec. 5.3.2) and of the flooded
+ * area (flood lines, sec. 6.4.3), restarted from the current state: zero
+ * rates and volumes, h_max = h, t_wet = t on wet cells. */
+void ora_reset_monitors(ora *o)
+{
+    memset(o->brate, 0, o->ne * sizeof(double));
+    memset(o->bvol, 0, o->ne * sizeof(double));
+    for (int64_t i = 0; i < o->nc; ++i) {
+        o->hmax[i] = o->h[i];
+        o->twet[i] = o->h[i] > o->h_dry ? o->t : INFINITY;
+    }
+}
+
+/* Rate [m^3/s] of the last step and volume [m^3] since the reset leaving
+ * the domain through the boundary edges of one tag, summed in edge order. */
+void ora_discharge(const ora *o, int tag, double *rate, double *volume)
+{
+    double r = 0.0, v = 0.0;
+    for (int64_t e = 0; e < o->ne; ++e)
+        if (o->e_right[e] < 0 && o->e_tag[e] == tag) {
+            r += o->brate[e];
+            v += o->bvol[e];
+        }
+    *rate = r;
+    *volume = v;
+}
+
+void ora_envelope(const ora *o, double *hmax, double *twet)
+{
+    memcpy(hmax, o->hmax, o->nc * sizeof(double));
+    memcpy(twet, o->twet, o->nc * sizeof(double));
 }
 
 void ora_get_state(const ora *o, double *h, double *hu, double *hv)
@@ -749,6 +795,14 @@ int ora_run(ora *o, int64_t max_steps, double t_end, int nthreads,
                                   o->e_ny[e], o->e_len[e], &o->cl[3 * e]);
             }
         }
+        /* monitors: a boundary edge's contribution to its cell is
+           cl = -L F with F_1 = G_1, the outward normal mass flux, so the
+           volume leaving per unit time is L G_1 = -cl_1 */
+        for (int64_t e = 0; e < o->ne; ++e)
+            if (o->e_right[e] < 0) {
+                o->brate[e] = -o->cl[3 * e];
+                o->bvol[e] += dt * o->brate[e];
+            }
         /* cell loop: the new state is written in place once every edge of
            the step has been evaluated */
         int bad = 0;
@@ -768,6 +822,8 @@ int ora_run(ora *o, int64_t max_steps, double t_end, int nthreads,
             o->h[i] = out[0];
             o->hu[i] = out[1];
             o->hv[i] = out[2];
+            if (out[0] > o->hmax[i]) o->hmax[i] = out[0];
+            if (o->twet[i] == INFINITY && out[0] > h_dry) o->twet[i] = tn;
             if (!isfinite(out[0]) || !isfinite(out[1]) || !isfinite(out[2]))
                 bad = 1;
         }

@@ -33,6 +33,9 @@ struct DevBufs {
     Clock *clock;
     double *ledger;
     int32_t *quiet;
+    double *mon_rate, *mon_vol;   // per boundary slot
+    int32_t *blk_bnd, *blk_bnd_rec;
+    double *h_max, *t_wet;        // per cell (internal order)
     double *part_mass;
     unsigned long long *part_wet;
     unsigned *flag;
@@ -53,7 +56,8 @@ struct swe_ctx {
     std::vector<double> z, man, h, hu, hv;
     bool z_dirty = false, man_dirty = false, state_dirty = false;
     bool gm2_dirty = true;
-    std::vector<BcEntry> bc;
+    std::vector<BcEntry> bc;        // per tag
+    std::vector<BcEntry> bc_slot;   // per boundary slot
     bool bc_dirty = true;
     // device
     bool dev_ready = false;
@@ -72,6 +76,7 @@ struct swe_ctx {
     long long step_index = 0;  // steps launched since the mesh was set
     bool uploaded = false;     // host memory queued on the stream
     bool quiet_dirty = true;   // state buffers written outside a step
+    bool mon_dirty = true;     // monitors to be reset before the next step
 };
 
 namespace {
@@ -128,10 +133,17 @@ size_t layout(const BlockMesh &m, char *base, DevBufs *d)
     t.be_nx = (double *)take(nbe * 8);
     t.be_ny = (double *)take(nbe * 8);
     t.be_len = (double *)take(nbe * 8);
-    t.bc = (BcEntry *)take(sizeof(BcEntry) * SWE_MAX_TAG);
+    const size_t nbnd = m.bnd_tag.size() > 0 ? m.bnd_tag.size() : 1;
+    t.bc = (BcEntry *)take(sizeof(BcEntry) * nbnd);
     t.clock = (Clock *)take(sizeof(Clock));
     t.ledger = (double *)take(nb * 8);
     t.quiet = (int32_t *)take(nb * 4);
+    t.mon_rate = (double *)take(nbnd * 8);
+    t.blk_bnd = (int32_t *)take((nb + 1) * 4);
+    t.blk_bnd_rec = (int32_t *)take(nb * 4);
+    t.mon_vol = (double *)take(nbnd * 8);
+    t.h_max = (double *)take(nc * 8);
+    t.t_wet = (double *)take(nc * 8);
     t.part_mass = (double *)take(kDiagParts * 8);
     t.part_wet = (unsigned long long *)take(kDiagParts * 8);
     t.flag = (unsigned *)take(256);
@@ -160,6 +172,8 @@ swe_status upload(swe_ctx *c, T *dst, const T *src, size_t n)
     c->uploaded = true;
     return SWE_OK;
 }
+
+swe_status read_clock(swe_ctx *c, Clock *out);
 
 // Allocates (or adopts) the workspace and uploads whatever the host holds
 // newer than the device.
@@ -193,6 +207,11 @@ swe_status prepare(swe_ctx *c)
         if ((st = upload(c, d.user_of_internal, m.user_of_internal.data(), nc)))
             return st;
         if ((st = upload(c, d.blk_edge, m.blk_edge.data(), m.blk_edge.size())))
+            return st;
+        if ((st = upload(c, d.blk_bnd, m.blk_bnd.data(), m.blk_bnd.size())))
+            return st;
+        if ((st = upload(c, d.blk_bnd_rec, m.blk_bnd_rec.data(),
+                         m.blk_bnd_rec.size())))
             return st;
         const size_t nbe = m.be_a.size();
         if ((st = upload(c, d.be_a, m.be_a.data(), nbe))) return st;
@@ -229,6 +248,7 @@ swe_status prepare(swe_ctx *c)
         c->state_dirty = false;
         c->dt_valid = false;
         c->quiet_dirty = true;
+        c->mon_dirty = true;
     }
     if (c->quiet_dirty) {
         // the step kernel may skip stores only after two steps from here
@@ -237,13 +257,17 @@ swe_status prepare(swe_ctx *c)
         c->quiet_dirty = false;
     }
     if (c->bc_dirty) {
-        // inflow discharge per unit length of each tag
+        // inflow discharge per unit length of each tag, then one entry per
+        // boundary slot
         for (int k = 0; k < SWE_MAX_TAG; ++k) {
             BcEntry &b = c->bc[k];
             const double L = c->mesh.tag_length[k];
             b.q = (b.kind == SWE_BC_INFLOW && L > 0.0) ? b.value / L : 0.0;
         }
-        if ((st = upload(c, d.bc, c->bc.data(), SWE_MAX_TAG))) return st;
+        const std::vector<int32_t> &bt = c->mesh.bnd_tag;
+        c->bc_slot.resize(bt.size());
+        for (size_t k = 0; k < bt.size(); ++k) c->bc_slot[k] = c->bc[bt[k]];
+        if ((st = upload(c, d.bc, c->bc_slot.data(), bt.size()))) return st;
         c->bc_dirty = false;
     }
     if (c->clock_dirty) {
@@ -251,6 +275,19 @@ swe_status prepare(swe_ctx *c)
                                         c->stream));
         c->clock_dirty = false;
         c->dt_valid = false;
+    }
+    if (c->params.monitors && c->mon_dirty) {
+        if (!c->t_known) {
+            Clock ck;
+            if ((st = read_clock(c, &ck))) return st;
+        }
+        const size_t nbnd = c->mesh.bnd_tag.size();
+        HIPCHK(c, swe::launch_fill_f64(d.mon_rate, 0.0, nbnd, c->stream));
+        HIPCHK(c, swe::launch_fill_f64(d.mon_vol, 0.0, nbnd, c->stream));
+        HIPCHK(c, swe::launch_envelope_reset(d.h[c->cur_buf], nc,
+                                             c->params.h_dry, c->t_host,
+                                             d.h_max, d.t_wet, c->stream));
+        c->mon_dirty = false;
     }
     if (!c->dt_valid) {
         // min over wet cells of R_i / s_i of the current state, into the
@@ -363,6 +400,8 @@ swe_status swe_default_params(swe_params *p)
     p->reorder = 1;
     p->block_threads = 0;
     p->load_schedule = 0;
+    p->monitors = 0;
+    p->store_all = 0;
     p->reserved = 0;
     return SWE_OK;
 }
@@ -432,10 +471,14 @@ swe_status swe_set_params(swe_ctx *c, const swe_params *p)
                     "block_threads must be 0, block_cells or 2*block_cells");
     if (p->load_schedule != 0 && p->load_schedule != 1)
         return fail(c, SWE_EINVAL, "load_schedule must be 0 or 1");
-
+    if (p->monitors != 0 && p->monitors != 1)
+        return fail(c, SWE_EINVAL, "monitors must be 0 or 1");
+    if (p->store_all != 0 && p->store_all != 1)
+        return fail(c, SWE_EINVAL, "store_all must be 0 or 1");
     if (p->reserved != 0) return fail(c, SWE_EINVAL, "reserved must be 0");
     const bool g_changed = p->g != c->params.g;
     const bool dt_changed = g_changed || p->h_dry != c->params.h_dry;
+    if (p->monitors && !c->params.monitors) c->mon_dirty = true;
     c->params = *p;
     if (g_changed) c->gm2_dirty = true;
     if (dt_changed) c->dt_valid = false;
@@ -597,6 +640,7 @@ swe_status swe_set_state(swe_ctx *c, const double *h, const double *hu,
                                   c->stream));
     c->dt_valid = false;
     c->quiet_dirty = true;
+    c->mon_dirty = true;
     return prepare(c);
 }
 
@@ -690,6 +734,15 @@ swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
     a.clock = c->d.clock;
     a.ledger = c->d.ledger;
     a.quiet = c->d.quiet;
+    a.store_all = c->params.store_all;
+    if (c->params.monitors) {
+        a.mon_rate = c->d.mon_rate;
+        a.mon_vol = c->d.mon_vol;
+        a.blk_bnd = c->d.blk_bnd;
+        a.blk_bnd_rec = c->d.blk_bnd_rec;
+        a.h_max = c->d.h_max;
+        a.t_wet = c->d.t_wet;
+    }
     a.g = c->params.g;
     a.cfl = c->params.cfl;
     a.h_dry = c->params.h_dry;
@@ -779,6 +832,78 @@ swe_status swe_get_diagnostics(swe_ctx *c, double *mass, double *ledger,
     if (mass) *mass = s;
     if (ledger) *ledger = l;
     if (n_wet) *n_wet = int64_t(w);
+    return SWE_OK;
+}
+
+swe_status swe_reset_monitors(swe_ctx *c)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    c->mon_dirty = true;
+    if (!c->params.monitors) return SWE_OK;
+    return prepare(c);
+}
+
+swe_status swe_get_discharge(swe_ctx *c, int32_t tag, double *rate,
+                             double *volume)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    if (tag < 0 || tag >= SWE_MAX_TAG)
+        return fail(c, SWE_EINVAL, "tag out of range");
+    if (!c->params.monitors)
+        return fail(c, SWE_ENOTREADY, "monitors are off (swe_params.monitors)");
+    if ((st = prepare(c))) return st;
+    const std::vector<int32_t> &bt = c->mesh.bnd_tag;
+    std::vector<double> r(bt.size()), v(bt.size());
+    if (!bt.empty()) {
+        HIPCHK(c, hipMemcpyAsync(r.data(), c->d.mon_rate, bt.size() * 8,
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(v.data(), c->d.mon_vol, bt.size() * 8,
+                                 hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double sr = 0.0, sv = 0.0;
+    for (size_t k = 0; k < bt.size(); ++k)
+        if (bt[k] == tag) {
+            sr += r[k];
+            sv += v[k];
+        }
+    if (rate) *rate = sr;
+    if (volume) *volume = sv;
+    return SWE_OK;
+}
+
+swe_status swe_get_envelope(swe_ctx *c, double *h_max, double *t_wet,
+                            swe_mem mem)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    if (!h_max || !t_wet) return fail(c, SWE_EINVAL, "null envelope array");
+    if (!c->params.monitors)
+        return fail(c, SWE_ENOTREADY, "monitors are off (swe_params.monitors)");
+    if ((st = prepare(c))) return st;
+    const int64_t nc = c->mesh.n_cells;
+    if (mem == SWE_MEM_DEVICE) {
+        HIPCHK(c, swe::launch_gather1(c->d.h_max, h_max,
+                                      c->d.internal_of_user, nc, c->stream));
+        HIPCHK(c, swe::launch_gather1(c->d.t_wet, t_wet,
+                                      c->d.internal_of_user, nc, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return SWE_OK;
+    }
+    if (mem != SWE_MEM_HOST) return fail(c, SWE_EINVAL, "bad memory kind");
+    std::vector<double> a(nc), b(nc);
+    HIPCHK(c, hipMemcpyAsync(a.data(), c->d.h_max, nc * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b.data(), c->d.t_wet, nc * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int64_t u = 0; u < nc; ++u) {
+        const int32_t i = c->mesh.internal_of_user[u];
+        h_max[u] = a[i];
+        t_wet[u] = b[i];
+    }
     return SWE_OK;
 }
 

@@ -48,7 +48,7 @@ struct StepArgs {
     const double *gm2;        // g m^2 per cell
     const double *area;
     const double *inradius;
-    const BcEntry *bc;
+    const BcEntry *bc;        // per boundary slot
     // state: U^n in, U^{n+1} out
     const double *h0;
     const double *hu0;
@@ -60,9 +60,19 @@ struct StepArgs {
     double *ledger;           // per block: mass added by the positivity fix
     int32_t *quiet;           // per block: consecutive steps (capped at 2) in
                               // which every cell took the quiet dry path
+    // monitors (all null when off): per boundary slot the outward volume
+    // rate of the last step and the volume since the last reset; per cell
+    // the highest depth and the first time with h > h_dry (+inf: never)
+    double *mon_rate;
+    double *mon_vol;
+    const int32_t *blk_bnd;       // per block: first boundary slot (+1 entry)
+    const int32_t *blk_bnd_rec;   // per block: record of its first slot
+    double *h_max;
+    double *t_wet;
     double g, cfl, h_dry, dt_max, t_end;
     int32_t n_cells;
     int32_t n_blocks;
+    int32_t store_all;        // 1: every cell stores every step
     int32_t cur;              // clock slot of this step
     long long step_index;
 };
@@ -98,6 +108,10 @@ hipError_t launch_diag(const double *h, const double *area, int64_t n,
                        hipStream_t s);
 hipError_t launch_fill_u32(unsigned *p, unsigned v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+// h_max = h; t_wet = t where h > h_dry, else +inf
+hipError_t launch_envelope_reset(const double *h, int64_t n, double h_dry,
+                                 double t, double *h_max, double *t_wet,
+                                 hipStream_t s);
 
 constexpr int kDiagThreads = 256;
 

@@ -334,7 +334,7 @@ struct Side {
     int kind;      // 0 cell of this block, 1 cell of another block, 2 boundary
     int local;     // kind 0: local cell index
     int k;         // kind 0: that cell's side along the edge
-    int global;    // kind 1: internal cell index; kind 2: boundary tag
+    int global;    // kind 1: internal cell index; kind 2: boundary slot
 };
 
 __device__ __forceinline__ Side decode_side(int32_t v)
@@ -350,7 +350,7 @@ __device__ __forceinline__ Side decode_side(int32_t v)
         s.kind = 2;
         s.local = 0;
         s.k = 0;
-        s.global = int(u & 0x3ffu);
+        s.global = int(u & 0x3fffffffu);
     } else {
         s.kind = 1;
         s.local = 0;
@@ -440,8 +440,9 @@ __device__ __forceinline__ int xcd_block(int w, int n_blocks)
 // of an edge between two cells holding no water is never read, and a dry
 // cell reads its area and inscribed radius only if it receives flux.
 // Both read the same values and round identically.
-template <int NC, int NT, bool EAGER>
-__global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
+template <int NC, int NT, bool EAGER, bool MON>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6)))
+void swe_step_kernel(StepArgs a)
 {
     extern __shared__ double lds[];
     __shared__ double red_min[NT / 64];
@@ -571,6 +572,7 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
             edge_contrib(g, h_dry, pb.kind == 2, bc, Lc, Rc, enx, eny, elen,
                          cl0, cl1, cl2, cr0, cr1, cr2);
         }
+
         if (pa.kind == 0) {
             double *d = s_c + pa.k * NC + pa.local;
             d[0] = cl0;
@@ -654,15 +656,36 @@ __global__ __launch_bounds__(NT) void swe_step_kernel(StepArgs a)
         }
         // a quiet cell of a block quiet in the two previous steps already
         // holds (h, 0, 0) in the output buffer (it held U^{n-1} = U^n)
-        if (active || quiet_steps < 2) {
+        if (active || quiet_steps < 2 || a.store_all) {
             a.h1[i] = hn;
             a.hu1[i] = hun;
             a.hv1[i] = hvn;
+        }
+        if (MON && hn > hc) {
+            // flood envelope: the depth only rises where hn > h, and
+            // h_max >= h always holds
+            const double hm = a.h_max[i];
+            if (hn > hm) {
+                a.h_max[i] = hn;
+                if (hm <= h_dry && hn > h_dry) a.t_wet[i] = st.tn;
+            }
         }
         if (!isfinite(hn) || !isfinite(hun) || !isfinite(hvn)) bad = 1u;
         if (hn > h_dry) {
             const double u = hun / hn, v = hvn / hn;
             rs = inr / (sqrt(g * hn) + sqrt(u * u + v * v));
+        }
+    }
+    if (MON) {
+        // discharge monitors: the volume leaving through each boundary edge
+        // per unit time, L G_1 = -(its mass contribution to its cell), read
+        // back from the cell's side slot
+        const int s0 = a.blk_bnd[blk], nbnd = a.blk_bnd[blk + 1] - s0;
+        for (int k = tid; k < nbnd; k += NT) {
+            const Side pa = decode_side(a.be_a[a.blk_bnd_rec[blk] + k]);
+            const double rate = -s_c[pa.k * NC + pa.local];
+            a.mon_rate[s0 + k] = rate;
+            a.mon_vol[s0 + k] += st.dt * rate;
         }
     }
     block_finish<NT>(a, blk, rs, clamp, bad, active, quiet_steps,
@@ -833,6 +856,17 @@ __global__ __launch_bounds__(256) void fill_f64_kernel(double *p, double v,
         p[k] = v;
 }
 
+__global__ __launch_bounds__(256) void envelope_reset_kernel(
+    const double *h, int64_t n, double h_dry, double t, double *h_max,
+    double *t_wet)
+{
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n;
+         k += int64_t(gridDim.x) * blockDim.x) {
+        h_max[k] = h[k];
+        t_wet[k] = h[k] > h_dry ? t : INFINITY;
+    }
+}
+
 inline unsigned grid_for(int64_t n, int threads = 256)
 {
     int64_t b = (n + threads - 1) / threads;
@@ -849,15 +883,26 @@ size_t step_lds_bytes(int block_cells)
 }
 
 namespace {
+template <int NC, int NT, bool MON>
+void launch_mon(const StepArgs &a, int schedule, hipStream_t s)
+{
+    if (schedule == 0)
+        hipLaunchKernelGGL((swe_step_kernel<NC, NT, false, MON>),
+                           dim3(a.n_blocks), dim3(NT), step_lds_bytes(NC), s,
+                           a);
+    else
+        hipLaunchKernelGGL((swe_step_kernel<NC, NT, true, MON>),
+                           dim3(a.n_blocks), dim3(NT), step_lds_bytes(NC), s,
+                           a);
+}
+
 template <int NC, int NT>
 void launch_one(const StepArgs &a, int schedule, hipStream_t s)
 {
-    if (schedule == 0)
-        hipLaunchKernelGGL((swe_step_kernel<NC, NT, false>), dim3(a.n_blocks),
-                           dim3(NT), step_lds_bytes(NC), s, a);
+    if (a.mon_rate)
+        launch_mon<NC, NT, true>(a, schedule, s);
     else
-        hipLaunchKernelGGL((swe_step_kernel<NC, NT, true>), dim3(a.n_blocks),
-                           dim3(NT), step_lds_bytes(NC), s, a);
+        launch_mon<NC, NT, false>(a, schedule, s);
 }
 }  // namespace
 
@@ -973,6 +1018,15 @@ hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(n)), dim3(256), 0, s, p,
                        v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_envelope_reset(const double *h, int64_t n, double h_dry,
+                                 double t, double *h_max, double *t_wet,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(envelope_reset_kernel, dim3(grid_for(n)), dim3(256), 0,
+                       s, h, n, h_dry, t, h_max, t_wet);
     return hipGetLastError();
 }
 

@@ -411,7 +411,8 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
     //        in the block:  kSideLocal | k << 12 | local cell   (k = the
     //                       cell's side along this edge, 0..2)
     //        other block:   internal cell index (< 2^30)
-    //        boundary:      kSideBoundary | tag   (right side only)
+    //        boundary:      kSideBoundary | boundary slot (right side
+    //                       only; slots numbered in block order)
     const int32_t B = block_cells;
     const int64_t nblk = (nc + B - 1) / B;
     if (nc >= (int64_t(1) << 30)) {
@@ -438,21 +439,39 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
         }
     }
     int32_t emax = 0;
+    std::vector<int64_t> blk_bnd(nblk + 1, 0);   // boundary slots per block
+    std::vector<int32_t> n_cross(nblk, 0);        // edges to another block
 #pragma omp parallel for schedule(static) reduction(max : emax)
     for (int64_t b = 0; b < nblk; ++b) {
         const int64_t c0 = b * B, c1 = std::min<int64_t>(nc, c0 + B);
-        int32_t n = 0;
+        int32_t n = 0, nbnd = 0;
         for (int64_t i = c0; i < c1; ++i)
             for (int k = 0; k < 3; ++k) {
                 const int64_t j = side_nb[3 * i + k];
                 if (j < 0 || j < c0 || j >= c1 || i < j) ++n;
+                if (j < 0) ++nbnd;
+                else if (j < c0 || j >= c1) ++n_cross[b];
             }
         M.blk_cell[b] = int32_t(c0);
         M.blk_edge[b + 1] = n;
+        blk_bnd[b + 1] = nbnd;
         emax = std::max(emax, n);
     }
     M.blk_cell[nblk] = int32_t(nc);
-    for (int64_t b = 0; b < nblk; ++b) M.blk_edge[b + 1] += M.blk_edge[b];
+    for (int64_t b = 0; b < nblk; ++b) {
+        M.blk_edge[b + 1] += M.blk_edge[b];
+        blk_bnd[b + 1] += blk_bnd[b];
+    }
+    if (blk_bnd[nblk] >= (int64_t(1) << 30)) {
+        err = "mesh too large: at most 2^30 boundary edges";
+        return false;
+    }
+    M.bnd_tag.resize(blk_bnd[nblk]);
+    M.blk_bnd.resize(nblk + 1);
+    M.blk_bnd_rec.resize(nblk);
+    for (int64_t b = 0; b <= nblk; ++b) M.blk_bnd[b] = int32_t(blk_bnd[b]);
+    for (int64_t b = 0; b < nblk; ++b)
+        M.blk_bnd_rec[b] = M.blk_edge[b] + n_cross[b];
     M.max_block_edges = emax;
     const int64_t nbe = M.blk_edge[nblk];
     M.be_a.resize(nbe);
@@ -483,7 +502,7 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
                 return int32_t(kSideLocal | (uint32_t(kk) << 12) |
                                uint32_t(j - c0));
             };
-            int64_t at = M.blk_edge[b];
+            int64_t at = M.blk_edge[b], slot = blk_bnd[b];
             for (int g = 0; g < 3; ++g)
                 for (const Use &use : grp[g]) {
                     const int32_t e = use.e;
@@ -491,7 +510,8 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
                     const bool l_in = il >= c0 && il < c1;
                     M.be_a[at] = l_in ? local_code(il, e) : int32_t(il);
                     if (e_right[e] < 0) {
-                        M.be_b[at] = int32_t(kSideBoundary | uint32_t(e_tag[e]));
+                        M.be_b[at] = int32_t(kSideBoundary | uint32_t(slot));
+                        M.bnd_tag[slot++] = e_tag[e];
                     } else {
                         const int64_t ir = iou[e_right[e]];
                         const bool r_in = ir >= c0 && ir < c1;

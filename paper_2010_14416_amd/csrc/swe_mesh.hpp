@@ -36,10 +36,16 @@ struct BlockMesh {
     //   kSideLocal | k << 12 | c : cell c of the block (local index), whose
     //                              local side k is this edge
     //   i (>= 0, < 2^30)         : internal index of a cell of another block
-    //   kSideBoundary | tag      : boundary (right side only)
+    //   kSideBoundary | s        : boundary slot s (right side only)
     // and the unit normal from left to right (outward on the boundary).
     std::vector<int32_t> be_a, be_b;
     std::vector<double> be_nx, be_ny, be_len;
+
+    // tag of each boundary slot; slots are numbered in block order. Block b
+    // holds slots [blk_bnd[b], blk_bnd[b+1]), whose records are consecutive
+    // from record blk_bnd_rec[b] on (after the edges to other blocks).
+    std::vector<int32_t> bnd_tag;
+    std::vector<int32_t> blk_bnd, blk_bnd_rec;
 
     // total boundary length per tag (inflow discharge per unit length)
     std::vector<double> tag_length;

@@ -46,6 +46,7 @@ class swe_params(C.Structure):
                 ("dt_max", C.c_double), ("check_every", C.c_int32),
                 ("block_cells", C.c_int32), ("reorder", C.c_int32),
                 ("block_threads", C.c_int32), ("load_schedule", C.c_int32),
+                ("monitors", C.c_int32), ("store_all", C.c_int32),
                 ("reserved", C.c_int32)]
 
 
@@ -131,6 +132,12 @@ def load():
     L.swe_advance.argtypes = [_p, C.c_int64, C.c_double, _pi64, _pd]
     L.swe_get_diagnostics.restype = st
     L.swe_get_diagnostics.argtypes = [_p, _pd, _pd, _pi64]
+    L.swe_reset_monitors.restype = st
+    L.swe_reset_monitors.argtypes = [_p]
+    L.swe_get_discharge.restype = st
+    L.swe_get_discharge.argtypes = [_p, C.c_int32, _pd, _pd]
+    L.swe_get_envelope.restype = st
+    L.swe_get_envelope.argtypes = [_p, _p, _p, C.c_int]
     L.swe_workspace_bytes.restype = st
     L.swe_workspace_bytes.argtypes = [_p, C.POINTER(C.c_size_t)]
     L.swe_bind_workspace.restype = st
@@ -335,6 +342,34 @@ def swe_get_diagnostics(ctx):
     return m.value, led.value, nw.value
 
 
+def swe_reset_monitors(ctx):
+    _check(ctx, load().swe_reset_monitors(ctx))
+
+
+def swe_get_discharge(ctx, tag):
+    """(rate [m^3/s] of the last step, volume [m^3] since the reset) leaving
+    the domain through boundary tag `tag`."""
+    r, v = C.c_double(), C.c_double()
+    _check(ctx, load().swe_get_discharge(ctx, int(tag), C.byref(r),
+                                         C.byref(v)))
+    return r.value, v.value
+
+
+def swe_get_envelope(ctx, out=None):
+    """Returns (h_max, t_wet) as numpy arrays, or fills `out` (two float64
+    CUDA tensors or numpy arrays) and returns it."""
+    nc = _n_cells(ctx)
+    if out is None:
+        out = (np.empty(nc), np.empty(nc))
+    ptrs = [_cell_ptr(a, nc, "out") for a in out]
+    mems = {m for _, m, _ in ptrs}
+    if len(mems) != 1:
+        raise ValueError("outputs must all be host or all device arrays")
+    _check(ctx, load().swe_get_envelope(ctx, ptrs[0][0], ptrs[1][0],
+                                        mems.pop()))
+    return out
+
+
 def swe_workspace_bytes(ctx):
     b = C.c_size_t()
     _check(ctx, load().swe_workspace_bytes(ctx, C.byref(b)))
@@ -408,6 +443,15 @@ class Solver:
 
     def diagnostics(self):
         return swe_get_diagnostics(self.ctx)
+
+    def discharge(self, tag):
+        return swe_get_discharge(self.ctx, tag)
+
+    def envelope(self, out=None):
+        return swe_get_envelope(self.ctx, out)
+
+    def reset_monitors(self):
+        swe_reset_monitors(self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):

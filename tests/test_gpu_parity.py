@@ -253,3 +253,59 @@ def test_state_reset_after_quiet_steps_is_bitwise():
     c.advance(25)
     for x, y in zip(c.state(), b.state()):
         assert np.array_equal(x, y)
+
+
+def test_monitors_match_the_oracle_and_leave_the_state_alone():
+    case = W.river(n_target=120_000, workers=1, steps=150)
+    say(f"[monitors] {case.name} cells={case.n_cells}")
+    s = solver(case, params={"monitors": 1})
+    s.advance(case.steps)
+    ref = solver(case)
+    ref.advance(case.steps)
+    for x, y in zip(s.state(), ref.state()):
+        assert np.array_equal(x, y)
+    o = O.Oracle(case)
+    o.run(case.steps)
+    q_in = case.bc[1][1]
+    vols = []
+    for tag in (0, 1, 2):
+        rg, vg = s.discharge(tag)
+        ro, vo = o.discharge(tag)
+        say(f"  tag {tag}: rate gpu={rg!r} ora={ro!r} vol gpu={vg!r} "
+            f"ora={vo!r}")
+        assert abs(rg - ro) <= 1e-9 * q_in
+        assert abs(vg - vo) <= 1e-9 * max(abs(vo), q_in * 1e-3)
+        vols.append(vg)
+    assert abs(s.discharge(1)[0] + q_in) <= 1e-12 * q_in
+    hm, tw = s.envelope()
+    om, ot = o.envelope()
+    assert rel_linf(hm, om) <= FULL_RUN
+    assert np.array_equal(np.isfinite(tw), np.isfinite(ot))
+    fin = np.isfinite(ot)
+    assert np.max(np.abs(tw[fin] - ot[fin]), initial=0.0) <= 1e-12 * max(
+        1.0, float(np.max(ot[fin], initial=0.0)))
+    assert np.all(hm >= s.state()[0])
+
+
+def test_monitors_closed_canal_reset_and_off():
+    from paper_2010_14416_amd import swe as S
+    case = W.dam_break_canal()
+    s = solver(case)
+    with pytest.raises(S.SweError) as e:
+        s.discharge(1)
+    assert e.value.status == S.SWE_ENOTREADY
+    p = S.swe_get_params(s.ctx)
+    p.monitors = 1
+    S.swe_set_params(s.ctx, p)
+    s.advance(30)
+    for tag in range(5):
+        assert s.discharge(tag) == (0.0, 0.0)
+    hm, tw = s.envelope()
+    h = s.state()[0]
+    assert np.all(hm >= h) and np.all(hm >= case.h - 1e-15)
+    # a reset starts over from the current state
+    s.reset_monitors()
+    hm2, tw2 = s.envelope()
+    t = s.time()[0]
+    assert np.array_equal(hm2, h)
+    assert np.array_equal(tw2, np.where(h > case.h_dry, t, np.inf))

@@ -19,7 +19,7 @@ import oracle as O
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PINS = ["tests/test_oracle_flux.py", "tests/test_oracle_cell.py",
-        "tests/test_oracle_scheme.py"]
+        "tests/test_oracle_scheme.py", "tests/test_oracle_monitors.py"]
 
 PLANTED = {
     # eq. 30 as printed: g instead of g/2 in the bed-slope term
@@ -74,6 +74,18 @@ PLANTED = {
     # velocity of the right cell taken from the left one
     "velocity_index": ("velocity(h_dry, hj, huj, hvj, &uj, &vj);",
                        "velocity(h_dry, hi, huj, hvj, &uj, &vj);"),
+    # monitors: inward instead of outward rate
+    "monitor_rate_sign": ("o->brate[e] = -o->cl[3 * e];",
+                          "o->brate[e] = o->cl[3 * e];"),
+    # monitors: volume summed without the time step
+    "monitor_volume_no_dt": ("o->bvol[e] += dt * o->brate[e];",
+                             "o->bvol[e] += o->brate[e];"),
+    # envelope: wetting time taken at the start of the step
+    "wet_time_start": ("o->twet[i] = tn;", "o->twet[i] = o->t;"),
+    # envelope: maximum tracked on wet cells only
+    "hmax_wet_only": ("if (out[0] > o->hmax[i]) o->hmax[i] = out[0];",
+                      "if (out[0] > o->hmax[i] && out[0] > h_dry) "
+                      "o->hmax[i] = out[0];"),
 }
 
 
