@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -174,10 +176,11 @@ def pmc_summary(fetch_csv, write_csv, copy_mb, n_cells, out_path):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (1000; 500 for the ensemble)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="river",
-                    choices=["river", "bumps", "canal"])
+                    choices=["river", "bumps", "canal", "ensemble"])
     ap.add_argument("--cells", type=int, default=13_000_000)
     ap.add_argument("--block-cells", type=int, default=256)
     ap.add_argument("--block-threads", type=int, default=0,
@@ -200,7 +203,14 @@ def main():
     ap.add_argument("--pmc-out", default=TRAFFIC_FILE)
     ap.add_argument("--pmc-cells", type=int, default=13_004_176,
                     help="cell count of the profiled workload")
+    ap.add_argument("--members", type=int, default=256,
+                    help="ensemble members (--workload ensemble)")
+    ap.add_argument("--solo-sample", type=int, default=16,
+                    help="ensemble members also timed one at a time")
+
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 500 if args.workload == "ensemble" else 1000
 
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_mb,
@@ -216,6 +226,9 @@ def main():
     import torch
     from paper_2010_14416_amd import Solver
 
+    if args.workload == "ensemble":
+        run_ensemble(args)
+        return
     t0 = time.perf_counter()
     case, desc = make_case(args)
     log(f"workload {case.name}: {case.n_cells} cells "
@@ -306,6 +319,89 @@ def main():
         roofline=roofline, cpu_baseline=base)
     print(json.dumps(out), flush=True)
     s.close()
+
+
+def run_ensemble(args):
+    """Batched ensemble of river runs (one launch per step for all members,
+    each with its own time step) against the same members advanced one at a
+    time: the per-member time of a sample of members run alone, scaled to
+    all members, over the ensemble's time."""
+    import torch
+    import workloads as W
+    from paper_2010_14416_amd import Ensemble, Solver
+
+    t0 = time.perf_counter()
+    cases = W.ensemble_members(n_members=args.members, steps=args.steps,
+                               workers=args.workers)
+    n = sum(c.n_cells for c in cases)
+    log(f"ensemble: {len(cases)} members, {n} cells "
+        f"({time.perf_counter() - t0:.1f} s to generate)")
+    t1 = time.perf_counter()
+    ens = Ensemble(cases, block_cells=args.block_cells,
+                   params={"block_threads": args.block_threads})
+    ens.advance(args.warmup)
+    ens.time(0)
+    setup_s = time.perf_counter() - t1
+    info = ens.info()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(ens.stream)
+    ens.advance(args.steps)
+    ev1.record(ens.stream)
+    torch.cuda.synchronize()
+    ens_ms = ev0.elapsed_time(ev1)
+    for k in range(len(cases)):
+        ens.time(k)                       # raises on a numeric fault
+    log(f"ensemble: {args.steps} steps in {ens_ms:.2f} ms "
+        f"({info['n_blocks']} blocks)")
+    ens.close()
+
+    k_sample = max(1, min(args.solo_sample, len(cases)))
+    pick = np.linspace(0, len(cases) - 1, k_sample).round().astype(int)
+    solo_ms, solo_cells = [], 0
+    for k in pick:
+        s = Solver(cases[k], device=0, block_cells=args.block_cells,
+                   params={"block_threads": args.block_threads})
+        s.advance(args.warmup, want_time=True)
+        torch.cuda.synchronize()
+        ev0.record(s.stream)
+        s.advance(args.steps)
+        ev1.record(s.stream)
+        torch.cuda.synchronize()
+        solo_ms.append(ev0.elapsed_time(ev1))
+        solo_cells += cases[k].n_cells
+        s.time()
+        s.close()
+    # one at a time, every member: the sample's time per cell-step scaled to
+    # all cells, and the sample's mean time per member
+    per_member_ms = float(np.mean(solo_ms))
+    solo_total_ms = per_member_ms * len(cases)
+    log(f"one at a time: {k_sample} members, {per_member_ms:.2f} ms each "
+        f"for {args.steps} steps")
+    value = n * args.steps / (ens_ms * 1e-3)
+    ms_per_step = ens_ms / args.steps
+    achieved = ALG_BYTES_PER_CELL * n / (ms_per_step * 1e-3) / 1e9
+    out = dict(
+        metric=METRIC, value=value, unit="cell-updates/s", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=ms_per_step,
+        higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload=f"ensemble-{len(cases)}: river runs of "
+                    "U[10k,200k] cells, Manning U[0.02,0.05], inflow "
+                    "U[200,800] m^3/s, own time step each",
+                    n_cells=n, members=len(cases), n_blocks=info["n_blocks"],
+                    setup_s=round(setup_s, 2), effective_gbs=achieved),
+        roofline=dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS,
+                      unit="GB/s", frac=achieved / PEAK_HBM_GBS,
+                      traffic=None, copy_gbs=None),
+        ensemble=dict(one_at_a_time_ms=solo_total_ms,
+                      one_at_a_time_ms_per_member=per_member_ms,
+                      sampled_members=int(k_sample),
+                      ensemble_ms=ens_ms,
+                      speedup_vs_one_at_a_time=solo_total_ms / ens_ms),
+        cpu_baseline=None)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

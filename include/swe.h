@@ -238,6 +238,46 @@ swe_status swe_get_discharge(swe_ctx *ctx, int32_t tag, double *rate,
 swe_status swe_get_envelope(swe_ctx *ctx, double *h_max, double *t_wet,
                             swe_mem mem);
 
+/* ------------------------------------------------------------------------
+ * Batched ensemble. The uncertainty studies behind the flood lines of
+ * sec. 6.4.3 run the solver hundreds of times with sampled inflow and
+ * friction; each run is a small mesh that leaves most of the GPU idle. An
+ * ensemble takes n configured contexts (mesh, bathymetry, Manning, boundary
+ * conditions, state and time as they stand; the contexts stay usable and
+ * independent) and advances all of them with one launch of the step kernel
+ * per step. Each member keeps its own time step, clock and end time, and
+ * its results are bitwise those of advancing its context alone.
+ *
+ * swe_ens_create: members must share g, cfl, h_dry, dt_max, block_cells and
+ * the device (SWE_EINVAL), and have a mesh (SWE_ENOTREADY). Copies what it
+ * needs; nothing is retained. The member's monitors are not kept.
+ * Errors of a failed create: swe_ens_last_error(NULL).
+ * swe_ens_advance: `steps` steps of every member; t_end[n_members] (NULL:
+ * all +INFINITY) stops each member at its own end time exactly (later
+ * steps of that member are empty). Asynchronous: only enqueues work.
+ * swe_ens_get_state / swe_ens_get_time: one member, user cell order; they
+ * synchronise the stream and return SWE_ENUMERIC if that member produced a
+ * non-finite state or an unbounded time step.
+ * swe_ens_workspace_bytes / swe_ens_bind_workspace: as for a context,
+ * before the first advance.
+ * swe_ens_info: cells of all members and mesh blocks. */
+typedef struct swe_ens swe_ens;
+
+swe_status swe_ens_create(swe_ens **out, swe_ctx *const *members,
+                          int32_t n_members);
+void swe_ens_destroy(swe_ens *ens);
+const char *swe_ens_last_error(const swe_ens *ens);
+swe_status swe_ens_set_stream(swe_ens *ens, void *hip_stream);
+swe_status swe_ens_workspace_bytes(swe_ens *ens, size_t *bytes);
+swe_status swe_ens_bind_workspace(swe_ens *ens, void *dev_ptr, size_t bytes);
+swe_status swe_ens_advance(swe_ens *ens, int64_t steps, const double *t_end);
+swe_status swe_ens_get_state(swe_ens *ens, int32_t member, double *h,
+                             double *hu, double *hv, swe_mem mem);
+swe_status swe_ens_get_time(swe_ens *ens, int32_t member, double *t,
+                            double *last_dt, int64_t *steps);
+swe_status swe_ens_info(const swe_ens *ens, int64_t *n_cells,
+                        int64_t *n_blocks);
+
 /* Device memory: by default the library allocates it on first use. A
  * caller that owns device memory (e.g. a torch uint8 tensor) can instead
  * bind a workspace of at least swe_workspace_bytes() bytes, 256-byte

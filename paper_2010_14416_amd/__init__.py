@@ -2,6 +2,6 @@
 Soulaimani, arXiv 2010.14416, sections 2-3): HIP kernels for gfx950 behind the
 C interface of include/swe.h, with a thin ctypes binding (``swe``)."""
 from . import swe  # noqa: F401
-from .swe import Solver, SweError, load  # noqa: F401
+from .swe import Ensemble, Solver, SweError, load  # noqa: F401
 
-__all__ = ["swe", "Solver", "SweError", "load"]
+__all__ = ["swe", "Ensemble", "Solver", "SweError", "load"]

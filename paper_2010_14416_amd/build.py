@@ -47,7 +47,7 @@ def build(verbose: bool = True) -> str:
         obj = os.path.join(BUILD, src + ".o")
         _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    for src in ["swe_mesh.cpp", "swe_api.cpp"]:
+    for src in ["swe_mesh.cpp", "swe_api.cpp", "swe_ensemble.cpp"]:
         obj = os.path.join(BUILD, src + ".o")
         _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

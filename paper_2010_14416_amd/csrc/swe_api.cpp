@@ -12,72 +12,15 @@
 #include <string>
 #include <vector>
 
+#include "swe_ctx.hpp"
 #include "swe_device.hpp"
 #include "swe_mesh.hpp"
 
 using swe::BcEntry;
 using swe::BlockMesh;
 using swe::Clock;
-
-namespace {
-
-// Device buffers, carved from one workspace (256-byte aligned pieces).
-struct DevBufs {
-    double *h[2], *hu[2], *hv[2];
-    double *z, *man, *gm2, *area, *inr;
-    int32_t *internal_of_user, *user_of_internal;
-    int32_t *blk_edge;
-    int32_t *be_a, *be_b;
-    double *be_nx, *be_ny, *be_len;
-    BcEntry *bc;
-    Clock *clock;
-    double *ledger;
-    int32_t *quiet;
-    double *mon_rate, *mon_vol;   // per boundary slot
-    int32_t *blk_bnd, *blk_bnd_rec;
-    double *h_max, *t_wet;        // per cell (internal order)
-    double *part_mass;
-    unsigned long long *part_wet;
-    unsigned *flag;
-};
-
-constexpr int kDiagParts = 1024;
-
-}  // namespace
-
-struct swe_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    swe_params params{};
-    std::string err;
-    bool has_mesh = false;
-    BlockMesh mesh;
-    // host copies in internal order; *_dirty: newer than the device copy
-    std::vector<double> z, man, h, hu, hv;
-    bool z_dirty = false, man_dirty = false, state_dirty = false;
-    bool gm2_dirty = true;
-    std::vector<BcEntry> bc;        // per tag
-    std::vector<BcEntry> bc_slot;   // per boundary slot
-    bool bc_dirty = true;
-    // device
-    bool dev_ready = false;
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
-    bool ws_owned = false;
-    DevBufs d{};
-    int cur_buf = 0;           // ping-pong buffer holding the current state
-    int cur_slot = 0;          // clock slot read by the next step
-    bool dt_valid = false;     // clock slot cur_slot holds min R/s of state
-    bool clock_dirty = true;   // host t/step must be pushed to the device
-    double t_host = 0.0;       // valid when t_known
-    bool t_known = true;
-    int64_t step_host = 0;
-    double last_dt_host = 0.0;
-    long long step_index = 0;  // steps launched since the mesh was set
-    bool uploaded = false;     // host memory queued on the stream
-    bool quiet_dirty = true;   // state buffers written outside a step
-    bool mon_dirty = true;     // monitors to be reset before the next step
-};
+using swe::DevBufs;
+using swe::kDiagParts;
 
 namespace {
 
@@ -750,6 +693,7 @@ swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
     a.t_end = t_end;
     a.n_cells = int32_t(m.n_cells);
     a.n_blocks = m.n_blocks;
+    a.blk_base = 0;
     const int threads = c->params.block_threads == 0
                             ? m.block_cells
                             : c->params.block_threads;

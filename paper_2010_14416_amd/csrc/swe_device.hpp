@@ -69,9 +69,17 @@ struct StepArgs {
     const int32_t *blk_bnd_rec;   // per block: record of its first slot
     double *h_max;
     double *t_wet;
+    // ensembles (all null for one mesh): per block its member, with the
+    // sign bit set on the member's first block; per member the end of its
+    // cell range and its end time; `clock` then points to one clock per
+    // member
+    const int32_t *blk_member;
+    const int32_t *member_end;
+    const double *t_end_m;
     double g, cfl, h_dry, dt_max, t_end;
     int32_t n_cells;
-    int32_t n_blocks;
+    int32_t n_blocks;         // blocks of this launch, from block blk_base
+    int32_t blk_base;
     int32_t store_all;        // 1: every cell stores every step
     int32_t cur;              // clock slot of this step
     long long step_index;

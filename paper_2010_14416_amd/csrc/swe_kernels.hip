@@ -280,6 +280,7 @@ __device__ __forceinline__ double wave_sum(double v)
 // advances the clock.
 template <int NT>
 __device__ __forceinline__ void block_finish(const StepArgs &a, int blk,
+                                             Clock *clock, bool first,
                                              double rs, double clamp,
                                              unsigned bad, bool active,
                                              int quiet_steps, bool unbounded,
@@ -311,20 +312,20 @@ __device__ __forceinline__ void block_finish(const StepArgs &a, int blk,
         const int q = (flags & 2u) ? 0 : min(quiet_steps + 1, 2);
         if (q != quiet_steps) a.quiet[blk] = q;
         if (m < INFINITY)
-            atomicMin(&a.clock->minrs[nxt][blockIdx.x & (kClockLanes - 1)][0],
+            atomicMin(&clock->minrs[nxt][blockIdx.x & (kClockLanes - 1)][0],
                       (unsigned long long)__double_as_longlong(m));
         if (cs != 0.0) a.ledger[blk] += cs;
         if (anybad || unbounded) {
-            atomicOr(&a.clock->health, (anybad ? 1u : 0u) | (unbounded ? 2u : 0u));
-            atomicMin(&a.clock->bad_step, a.step_index);
+            atomicOr(&clock->health, (anybad ? 1u : 0u) | (unbounded ? 2u : 0u));
+            atomicMin(&clock->bad_step, a.step_index);
         }
-        if (blk == 0) {
+        if (first) {
             const int nn = nxt == 2 ? 0 : nxt + 1;
-            a.clock->t[nxt] = tn;
-            a.clock->last_dt = dt;
-            if (dt > 0.0) a.clock->steps += 1;
+            clock->t[nxt] = tn;
+            clock->last_dt = dt;
+            if (dt > 0.0) clock->steps += 1;
             for (int x = 0; x < kClockLanes; ++x)
-                atomicExch(&a.clock->minrs[nn][x][0], kInfBits);
+                atomicExch(&clock->minrs[nn][x][0], kInfBits);
         }
     }
 }
@@ -370,10 +371,10 @@ struct StepTime {
 // Clock words of this step, read with one vector load per lane so that they
 // travel with the block's first loads: lane x < kClockLanes holds lane x of
 // the time-step minimum, lane kClockLanes the time t.
-__device__ __forceinline__ double clock_word(const StepArgs &a)
+__device__ __forceinline__ double clock_word(const StepArgs &a,
+                                             const Clock *c)
 {
     const int lane = int(threadIdx.x & 63u);
-    const Clock *c = a.clock;
     if (lane < kClockLanes)
         return __longlong_as_double((long long)c->minrs[a.cur][lane][0]);
     if (lane == kClockLanes) return c->t[a.cur];
@@ -388,7 +389,8 @@ __device__ __forceinline__ double read_lane(double v, int lane)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-__device__ __forceinline__ StepTime step_time(const StepArgs &a, double word)
+__device__ __forceinline__ StepTime step_time(const StepArgs &a, double word,
+                                              double t_end)
 {
     StepTime st;
     double mrs = read_lane(word, 0);
@@ -396,10 +398,10 @@ __device__ __forceinline__ StepTime step_time(const StepArgs &a, double word)
     for (int x = 1; x < kClockLanes; ++x) mrs = fmin(mrs, read_lane(word, x));
     const double t = read_lane(word, kClockLanes);
     st.dt = fmin(a.cfl * mrs, a.dt_max);
-    const double rem = a.t_end - t;
+    const double rem = t_end - t;
     if (st.dt >= rem) {
         st.dt = rem > 0.0 ? rem : 0.0;
-        st.tn = rem > 0.0 ? a.t_end : t;
+        st.tn = rem > 0.0 ? t_end : t;
     } else {
         st.tn = t + st.dt;
     }
@@ -455,9 +457,23 @@ void swe_step_kernel(StepArgs a)
     double *s_c = s_z + NC;   // [3 components][3 sides][NC cells]
 
     const int tid = threadIdx.x;
-    const int blk = xcd_block(blockIdx.x, a.n_blocks);
+    const int blk = a.blk_base + xcd_block(blockIdx.x, a.n_blocks);
     const int c0 = blk * NC;
-    const int nc = min(NC, a.n_cells - c0);
+    // one mesh, or member `mem` of an ensemble (its cells start on a block)
+    int mem = 0, cell_end = a.n_cells;
+    bool first = blk == 0;
+    if (a.blk_member) {
+        const int code = a.blk_member[blk];
+        first = code < 0;
+        mem = code & 0x7fffffff;
+        cell_end = a.member_end[mem];
+    }
+    Clock *clock = a.clock + mem;
+    const double t_end = a.t_end_m ? a.t_end_m[mem] : a.t_end;
+    const int nc = min(NC, cell_end - c0);
+    // an ensemble pads every member to whole blocks, so the block's NC
+    // cells can be read before the member's cell count has arrived
+    const int nc_read = a.blk_member ? NC : min(NC, a.n_cells - c0);
     const int e0 = a.blk_edge[blk];
     const int ne = a.blk_edge[blk + 1] - e0;
     const bool owner = tid < NC && tid < nc;
@@ -467,11 +483,11 @@ void swe_step_kernel(StepArgs a)
     // phase 1: owned cell, first edge record (+ geometry), neighbour state
     const int quiet_steps = a.quiet[blk];
     double h = 0.0, hu = 0.0, hv = 0.0, zc = 0.0;
-    if (owner) {
+    if (tid < NC && tid < nc_read) {
         h = a.h0[i];
         zc = a.z[i];
     }
-    const double cw = clock_word(a);
+    const double cw = clock_word(a, clock);
     int32_t ea = 0, eb = 0, ea2 = 0, eb2 = 0;
     double nx = 0.0, ny = 0.0, len = 0.0;
     if (tid < ne) {
@@ -515,7 +531,7 @@ void swe_step_kernel(StepArgs a)
             X.v = xhv / xh;
         }
     }
-    const StepTime st = step_time(a, cw);
+    const StepTime st = step_time(a, cw, t_end);
     if (owner) {
         s_h[tid] = h;
         s_z[tid] = zc;
@@ -688,8 +704,8 @@ void swe_step_kernel(StepArgs a)
             a.mon_vol[s0 + k] += st.dt * rate;
         }
     }
-    block_finish<NT>(a, blk, rs, clamp, bad, active, quiet_steps,
-                     st.unbounded, st.dt, st.tn,
+    block_finish<NT>(a, blk, clock, first, rs, clamp, bad, active,
+                     quiet_steps, st.unbounded, st.dt, st.tn,
                      a.cur == 2 ? 0 : a.cur + 1, red_min, red_sum, red_bad);
 }
 

@@ -138,6 +138,25 @@ def load():
     L.swe_get_discharge.argtypes = [_p, C.c_int32, _pd, _pd]
     L.swe_get_envelope.restype = st
     L.swe_get_envelope.argtypes = [_p, _p, _p, C.c_int]
+    L.swe_ens_create.restype = st
+    L.swe_ens_create.argtypes = [C.POINTER(_p), C.POINTER(_p), C.c_int32]
+    L.swe_ens_destroy.argtypes = [_p]
+    L.swe_ens_last_error.restype = C.c_char_p
+    L.swe_ens_last_error.argtypes = [_p]
+    L.swe_ens_set_stream.restype = st
+    L.swe_ens_set_stream.argtypes = [_p, _p]
+    L.swe_ens_workspace_bytes.restype = st
+    L.swe_ens_workspace_bytes.argtypes = [_p, C.POINTER(C.c_size_t)]
+    L.swe_ens_bind_workspace.restype = st
+    L.swe_ens_bind_workspace.argtypes = [_p, _p, C.c_size_t]
+    L.swe_ens_advance.restype = st
+    L.swe_ens_advance.argtypes = [_p, C.c_int64, _pd]
+    L.swe_ens_get_state.restype = st
+    L.swe_ens_get_state.argtypes = [_p, C.c_int32, _p, _p, _p, C.c_int]
+    L.swe_ens_get_time.restype = st
+    L.swe_ens_get_time.argtypes = [_p, C.c_int32, _pd, _pd, _pi64]
+    L.swe_ens_info.restype = st
+    L.swe_ens_info.argtypes = [_p, _pi64, _pi64]
     L.swe_workspace_bytes.restype = st
     L.swe_workspace_bytes.argtypes = [_p, C.POINTER(C.c_size_t)]
     L.swe_bind_workspace.restype = st
@@ -380,6 +399,71 @@ def swe_bind_workspace(ctx, ptr, nbytes):
     _check(ctx, load().swe_bind_workspace(ctx, C.c_void_p(ptr), int(nbytes)))
 
 
+# ---------------------------------------------------------------- ensemble
+
+def _echeck(ens, status):
+    if status != SWE_OK:
+        msg = load().swe_ens_last_error(ens)
+        raise SweError(status, msg.decode() if msg else "")
+
+
+def swe_ens_create(ctxs):
+    arr = (C.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    ens = C.c_void_p()
+    _echeck(None, load().swe_ens_create(C.byref(ens), arr, len(ctxs)))
+    return ens
+
+
+def swe_ens_destroy(ens):
+    load().swe_ens_destroy(ens)
+
+
+def swe_ens_set_stream(ens, stream):
+    _echeck(ens, load().swe_ens_set_stream(ens, C.c_void_p(stream)))
+
+
+def swe_ens_workspace_bytes(ens):
+    b = C.c_size_t()
+    _echeck(ens, load().swe_ens_workspace_bytes(ens, C.byref(b)))
+    return b.value
+
+
+def swe_ens_bind_workspace(ens, ptr, nbytes):
+    _echeck(ens, load().swe_ens_bind_workspace(ens, C.c_void_p(ptr),
+                                               int(nbytes)))
+
+
+def swe_ens_advance(ens, steps, t_end=None):
+    """t_end: None (all +inf) or one end time per member."""
+    if t_end is None:
+        _echeck(ens, load().swe_ens_advance(ens, int(steps), None))
+        return
+    t = np.ascontiguousarray(t_end, dtype=np.float64)
+    _echeck(ens, load().swe_ens_advance(
+        ens, int(steps), t.ctypes.data_as(_pd)))
+
+
+def swe_ens_get_state(ens, member, n_cells):
+    h, hu, hv = np.empty(n_cells), np.empty(n_cells), np.empty(n_cells)
+    _echeck(ens, load().swe_ens_get_state(
+        ens, int(member), h.ctypes.data, hu.ctypes.data, hv.ctypes.data,
+        SWE_MEM_HOST))
+    return h, hu, hv
+
+
+def swe_ens_get_time(ens, member):
+    t, dt, step = C.c_double(), C.c_double(), C.c_int64()
+    _echeck(ens, load().swe_ens_get_time(ens, int(member), C.byref(t),
+                                         C.byref(dt), C.byref(step)))
+    return t.value, dt.value, step.value
+
+
+def swe_ens_info(ens):
+    n, b = C.c_int64(), C.c_int64()
+    _echeck(ens, load().swe_ens_info(ens, C.byref(n), C.byref(b)))
+    return dict(n_cells=n.value, n_blocks=b.value)
+
+
 # ------------------------------------------------------------ convenience
 
 class Solver:
@@ -457,6 +541,69 @@ class Solver:
         if getattr(self, "ctx", None):
             swe_destroy(self.ctx)
             self.ctx = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ensemble:
+    """Members built from workloads.Case objects (each through a Solver with
+    no device memory of its own), advanced together. Device memory is a
+    torch uint8 tensor and kernels run on torch's current stream, unless
+    workspace / stream are None."""
+
+    def __init__(self, cases, device=0, block_cells=256, params=None,
+                 workspace="torch", stream="torch"):
+        self.members = [Solver(c, device=device, workspace=None, stream=None,
+                               block_cells=block_cells, params=params)
+                        for c in cases]
+        self.n_cells = [c.n_cells for c in cases]
+        self.ens = swe_ens_create([m.ctx for m in self.members])
+        self._ws = None
+        try:
+            if stream == "torch" or workspace == "torch":
+                import torch
+                dev = torch.device("cuda", device)
+                if stream == "torch":
+                    self.stream = torch.cuda.current_stream(dev)
+                    swe_ens_set_stream(self.ens, self.stream.cuda_stream)
+                if workspace == "torch":
+                    nb = swe_ens_workspace_bytes(self.ens)
+                    self._ws = torch.empty(nb + 256, dtype=torch.uint8,
+                                           device=dev)
+                    base = self._ws.data_ptr()
+                    swe_ens_bind_workspace(self.ens, base + (-base) % 256, nb)
+        except Exception:
+            self.close()
+            raise
+        # the members' host-side copies are no longer needed
+        for m in self.members:
+            m.close()
+        self.members = []
+
+    def advance(self, steps, t_end=None):
+        swe_ens_advance(self.ens, steps, t_end)
+
+    def state(self, member):
+        return swe_ens_get_state(self.ens, member, self.n_cells[member])
+
+    def time(self, member):
+        return swe_ens_get_time(self.ens, member)
+
+    def info(self):
+        return swe_ens_info(self.ens)
+
+
+    def close(self):
+        for m in getattr(self, "members", []):
+            m.close()
+        if getattr(self, "ens", None):
+            swe_ens_destroy(self.ens)
+            self.ens = None
         self._ws = None
 
     def __del__(self):

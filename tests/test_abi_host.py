@@ -186,3 +186,37 @@ def test_workspace_size_and_binding_checks(ctx):
     with pytest.raises(S.SweError) as e:
         S.swe_bind_workspace(ctx, 257, nb)
     assert e.value.status == S.SWE_EINVAL
+
+
+def test_ensemble_assembly_on_the_host():
+    """An ensemble is assembled on the host; members must agree on the
+    shared parameters."""
+    a = W.dam_break_canal()
+    b = W.bumps_canal(nx=20, ny=10)
+    ca, cb = S.swe_create(0), S.swe_create(0)
+    try:
+        for c, case in ((ca, a), (cb, b)):
+            S.swe_set_mesh(c, case.xy, case.tri, case.bnd, case.bnd_tag)
+            S.swe_set_state(c, case.h, case.hu, case.hv)
+        ens = S.swe_ens_create([ca, cb])
+        info = S.swe_ens_info(ens)
+        assert info["n_cells"] == a.n_cells + b.n_cells
+        ia, ib = S.swe_mesh_info(ca), S.swe_mesh_info(cb)
+        assert info["n_blocks"] == ia["n_blocks"] + ib["n_blocks"]
+        assert S.swe_ens_workspace_bytes(ens) > 0
+        S.swe_ens_destroy(ens)
+        p = S.swe_default_params()
+        p.cfl = 0.5
+        S.swe_set_params(cb, p)
+        with pytest.raises(S.SweError) as e:
+            S.swe_ens_create([ca, cb])
+        assert e.value.status == S.SWE_EINVAL
+        assert "differs" in S.load().swe_ens_last_error(None).decode()
+        empty = S.swe_create(0)
+        with pytest.raises(S.SweError) as e:
+            S.swe_ens_create([ca, empty])
+        assert e.value.status == S.SWE_ENOTREADY
+        S.swe_destroy(empty)
+    finally:
+        S.swe_destroy(ca)
+        S.swe_destroy(cb)

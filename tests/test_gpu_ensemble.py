@@ -1,0 +1,105 @@
+"""Batched ensemble on the GPU: every member advances exactly as its own
+context would (bitwise), with its own time step, clock and end time."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def members():
+    """Ragged mix: closed canal, dry-bed bumps, two river reaches with their
+    own inflow and friction, a lake at rest, and a two-cell mesh."""
+    r1 = W.river(n_target=30_000, workers=1, inflow_q=300.0)
+    r2 = W.river(n_target=12_000, workers=1, inflow_q=750.0)
+    r2.manning = np.full(r2.n_cells, 0.045)
+    xy = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], float)
+    tri = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    tiny = W.Case(name="two-triangles", xy=xy, tri=tri,
+                  bnd=np.zeros((0, 2), np.int32),
+                  bnd_tag=np.zeros(0, np.int32), bc={},
+                  z=np.array([0.0, 0.1]), manning=np.array([0.02, 0.03]),
+                  h=np.array([1.0, 0.2]), hu=np.array([0.1, 0.0]),
+                  hv=np.array([0.0, -0.05]))
+    return [W.dam_break_canal(), W.bumps_canal(nx=70, ny=23, lx=30.0,
+                                               ly=10.0, x_dam=15.0),
+            r1, r2, W.lake_at_rest(nx=40, ny=16), tiny]
+
+
+def solo(case, steps, t_end=math.inf):
+    from paper_2010_14416_amd import Solver
+    s = Solver(case, device=0)
+    if math.isfinite(t_end):
+        s.advance(10**6, t_end)
+    else:
+        s.advance(steps)
+    return s.state(), s.time()
+
+
+def test_members_match_their_own_runs_bitwise():
+    from paper_2010_14416_amd import Ensemble
+    cases = members()
+    say(f"[ensemble] sizes {[c.n_cells for c in cases]}")
+    ens = Ensemble(cases)
+    ens.advance(60)
+    for k, case in enumerate(cases):
+        (h, hu, hv), (t, dt, step) = solo(case, 60)
+        eh, ehu, ehv = ens.state(k)
+        et, edt, estep = ens.time(k)
+        say(f"  member {k} {case.name}: t={et!r} solo {t!r} steps {estep}")
+        assert np.array_equal(eh, h) and np.array_equal(ehu, hu)
+        assert np.array_equal(ehv, hv)
+        assert (et, edt, estep) == (t, dt, step)
+
+
+def test_members_stop_at_their_own_end_times():
+    from paper_2010_14416_amd import Ensemble
+    cases = members()[:4]
+    t_end = np.array([1.5, math.inf, 0.7, 2.0])
+    ens = Ensemble(cases)
+    ens.advance(400, t_end)
+    for k, case in enumerate(cases):
+        et, _, estep = ens.time(k)
+        if math.isfinite(t_end[k]):
+            assert et == t_end[k]
+            (h, hu, hv), (t, _, step) = solo(case, 0, t_end[k])
+        else:
+            (h, hu, hv), (t, _, step) = solo(case, 400)
+        assert et == t and estep == step
+        for x, y in zip(ens.state(k), (h, hu, hv)):
+            assert np.array_equal(x, y)
+
+
+def test_member_matches_the_oracle():
+    from paper_2010_14416_amd import Ensemble
+    case = W.river(n_target=20_000, workers=1, inflow_q=650.0)
+    ens = Ensemble([W.dam_break_canal(), case])
+    ens.advance(50)
+    o = O.Oracle(case)
+    o.run(50)
+    for x, y in zip(ens.state(1), o.state()):
+        d = float(np.max(np.abs(x - y)))
+        assert d <= 1e-9 * max(float(np.max(np.abs(y))), 1e-300)
+
+
+def test_a_failing_member_is_reported_alone():
+    from paper_2010_14416_amd import Ensemble, swe as S
+    dry = W.dam_break_canal(nx=10, ny=2, lx=10.0, ly=2.0, h_left=0.0,
+                            h_right=0.0)
+    ens = Ensemble([W.dam_break_canal(), dry])
+    ens.advance(3)
+    with pytest.raises(S.SweError) as e:
+        ens.time(1)
+    assert e.value.status == S.SWE_ENUMERIC
+    assert ens.time(0)[2] == 3
+

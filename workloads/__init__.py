@@ -434,14 +434,46 @@ def river(n_target: int = 13_000_000, seed: int = 3, n_strips: int = 16,
 # the three standard workloads
 # --------------------------------------------------------------------------
 
-def config(k: int, **kw) -> Case:
+def ensemble_members(n_members: int = 256, seed: int = 4,
+                     min_cells: int = 10_000, max_cells: int = 200_000,
+                     steps: int = 500, workers: int = 8) -> list:
+    """Uncertainty ensemble of river runs (the sampled inflow and friction of
+    sec. 6.4.3): member sizes ~ U[min_cells, max_cells] triangles, one
+    Manning coefficient n ~ U[0.02, 0.05] and one inflow Q ~ U[200, 800]
+    m^3/s per member, all on the reach and bed of the same seeded generator
+    (seed ``seed``) meshed at their own resolution. The draws come from
+    numpy SeedSequence(seed) in the order sizes, n, Q. Members are built in
+    ``workers`` threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    sizes = rng.integers(min_cells, max_cells + 1, n_members)
+    mann = rng.uniform(0.02, 0.05, n_members)
+    flow = rng.uniform(200.0, 800.0, n_members)
+
+    def one(k):
+        c = river(n_target=int(sizes[k]), seed=seed, inflow_q=float(flow[k]),
+                  steps=steps, workers=1)
+        c.manning = np.full(c.n_cells, float(mann[k]))
+        c.name = f"ensemble-member-{k}"
+        return c
+
+    if workers > 1:
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            return list(ex.map(one, range(n_members)))
+    return [one(k) for k in range(n_members)]
+
+
+def config(k: int, **kw):
     """Standard workloads: 1 dam-break canal (4 000 cells, to t = 5 s),
     2 bumps canal (1 000 000 cells, 2 000 steps), 3 river (about 13 M cells,
-    1 000 steps)."""
+    1 000 steps), 4 ensemble of 256 river runs (about 27 M cells in all, 500
+    steps each; a list of cases)."""
     if k == 1:
         return dam_break_canal(**kw)
     if k == 2:
         return bumps_canal(**kw)
     if k == 3:
         return river(**kw)
+    if k == 4:
+        return ensemble_members(**kw)
     raise ValueError(f"unknown workload {k}")
