@@ -205,6 +205,17 @@ swe_status swe_get_time(swe_ctx *ctx, double *t, double *last_dt,
 swe_status swe_advance(swe_ctx *ctx, int64_t max_steps, double t_end,
                        int64_t *steps_done, double *t_now);
 
+/* Frozen time-step schedule (for the adjoint and its finite-difference
+ * checks). Advances n steps: with dt non-NULL, step k takes dt[k] (host
+ * array, finite, >= 0) instead of the CFL time step, and no end time
+ * applies; with dt NULL the CFL time step as in swe_advance (t_end =
+ * +INFINITY). dt_out (host, n values, may be NULL) receives the time step of
+ * every step taken, so a run recorded with dt = NULL is replayed bit for
+ * bit by passing its dt_out back. The state must give bounded time steps.
+ * Synchronises the stream. */
+swe_status swe_advance_dt(swe_ctx *ctx, int64_t n, const double *dt,
+                          double *dt_out);
+
 /* Total water volume sum |Omega_i| h_i [m^3], the volume added by the
  * positivity fix since the mesh was set [m^3], and the number of cells
  * with h > h_dry. Synchronises the stream. */

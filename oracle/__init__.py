@@ -82,6 +82,7 @@ def lib():
         L.ora_mass.restype = _d
         L.ora_mass.argtypes = [_p]
         L.ora_run.argtypes = [_p, _i64, _d, _i, _pi64, _pd]
+        L.ora_run_dt.argtypes = [_p, _i64, _pd, _i]
         L.ora_reset_monitors.argtypes = [_p]
         L.ora_discharge.argtypes = [_p, _i, _pd, _pd]
         L.ora_envelope.argtypes = [_p, _pd, _pd]
@@ -242,6 +243,13 @@ class Oracle:
         if rc != 0:
             raise OracleError(lib().ora_error(self._h).decode())
         return done.value, t.value
+
+    def run_dt(self, dt):
+        """len(dt) steps, step k with time step dt[k]."""
+        d = np.ascontiguousarray(dt, dtype=np.float64)
+        if lib().ora_run_dt(self._h, d.size, _ptr(d, C.c_double),
+                            int(self.threads)) != 0:
+            raise OracleError(lib().ora_error(self._h).decode())
 
     def set_time(self, t: float, step: int = 0):
         lib().ora_set_time(self._h, t, step)

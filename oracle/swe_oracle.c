@@ -748,8 +748,28 @@ double ora_mass(const ora *o)
  * (the last step is shortened to land on t_end exactly). nthreads <= 0 keeps
  * the OpenMP default. Returns 0, or -1 with a message (ora_error) on a
  * non-finite state or an unbounded time step. */
+static int run_steps(ora *o, int64_t max_steps, double t_end,
+                     const double *dt_fixed, int nthreads,
+                     int64_t *steps_done, double *t_now);
+
 int ora_run(ora *o, int64_t max_steps, double t_end, int nthreads,
             int64_t *steps_done, double *t_now)
+{
+    return run_steps(o, max_steps, t_end, NULL, nthreads, steps_done, t_now);
+}
+
+/* n steps with a frozen schedule: step k takes dt[k] as its time step
+ * (the forward pass whose time steps an adjoint keeps fixed). */
+int ora_run_dt(ora *o, int64_t n, const double *dt, int nthreads)
+{
+    int64_t done;
+    double t;
+    return run_steps(o, n, INFINITY, dt, nthreads, &done, &t);
+}
+
+static int run_steps(ora *o, int64_t max_steps, double t_end,
+                     const double *dt_fixed, int nthreads,
+                     int64_t *steps_done, double *t_now)
 {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -767,12 +787,18 @@ int ora_run(ora *o, int64_t max_steps, double t_end, int nthreads,
                          ? o->bc[k].value / lsum[k] : 0.0;
     int64_t done = 0;
     while (done < max_steps && o->t < t_end) {
-        double m = ora_min_rs(o);
-        double dt = o->cfl * m;
-        if (dt > o->dt_max) dt = o->dt_max;
-        double rem = t_end - o->t, tn;
-        if (dt >= rem) { dt = rem; tn = t_end; }
-        else tn = o->t + dt;
+        double dt, tn;
+        if (dt_fixed) {
+            dt = dt_fixed[done];
+            tn = o->t + dt;
+        } else {
+            double m = ora_min_rs(o);
+            dt = o->cfl * m;
+            if (dt > o->dt_max) dt = o->dt_max;
+            double rem = t_end - o->t;
+            if (dt >= rem) { dt = rem; tn = t_end; }
+            else tn = o->t + dt;
+        }
         if (!(dt < INFINITY)) {
             snprintf(o->err, sizeof o->err,
                      "step %lld: no wet cell and no bound on the time step",

@@ -372,9 +372,10 @@ swe_status swe_create(swe_ctx **out, int device)
 void swe_destroy(swe_ctx *c)
 {
     if (!c) return;
-    if (c->ws_owned && c->ws) {
+    if ((c->ws_owned && c->ws) || c->dt_dev) {
         (void)hipSetDevice(c->device);
-        (void)hipFree(c->ws);
+        if (c->ws_owned && c->ws) (void)hipFree(c->ws);
+        if (c->dt_dev) (void)hipFree(c->dt_dev);
     }
     delete c;
 }
@@ -647,22 +648,27 @@ swe_status swe_get_time(swe_ctx *c, double *t, double *last_dt,
     return SWE_OK;
 }
 
-swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
-                       int64_t *steps_done, double *t_now)
+}  // extern "C"
+
+namespace swe {
+
+swe_status ctx_prepare(swe_ctx *c) { return prepare(c); }
+
+swe_status ctx_fail(swe_ctx *c, swe_status st, const std::string &msg)
 {
-    swe_status st = require_mesh(c);
-    if (st != SWE_OK) return st;
-    if (max_steps < 0) return fail(c, SWE_EINVAL, "max_steps < 0");
-    if (std::isnan(t_end)) return fail(c, SWE_EINVAL, "t_end is NaN");
-    if ((st = prepare(c))) return st;
+    return fail(c, st, msg);
+}
+
+swe_status ctx_read_clock(swe_ctx *c) 
+{
     Clock ck;
-    if (!c->t_known) {
-        if ((st = read_clock(c, &ck))) return st;
-    }
-    const int64_t steps0 = c->step_host;
-    int64_t done = 0;
+    return read_clock(c, &ck);
+}
+
+StepArgs ctx_step_args(swe_ctx *c, double t_end)
+{
     const BlockMesh &m = c->mesh;
-    swe::StepArgs a{};
+    StepArgs a{};
     a.blk_edge = c->d.blk_edge;
     a.be_a = c->d.be_a;
     a.be_b = c->d.be_b;
@@ -694,55 +700,134 @@ swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
     a.n_cells = int32_t(m.n_cells);
     a.n_blocks = m.n_blocks;
     a.blk_base = 0;
+    return a;
+}
+
+swe_status ctx_dt_buffer(swe_ctx *c, int64_t n)
+{
+    if (n <= c->dt_cap) return SWE_OK;
+    if (c->dt_dev) HIPCHK(c, hipFree(c->dt_dev));
+    c->dt_dev = nullptr;
+    c->dt_cap = 0;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, size_t(n) * 8);
+    if (e != hipSuccess)
+        return fail(c, SWE_ENOMEM, "time-step buffer: " +
+                                       std::string(hipGetErrorString(e)));
+    c->dt_dev = (double *)p;
+    c->dt_cap = n;
+    return SWE_OK;
+}
+
+swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
+                       const double *dt_fixed, double *dt_log)
+{
+    const BlockMesh &m = c->mesh;
     const int threads = c->params.block_threads == 0
                             ? m.block_cells
                             : c->params.block_threads;
-
-    auto launch_n = [&](int64_t n) -> swe_status {
-        for (int64_t k = 0; k < n; ++k) {
-            const int b = c->cur_buf;
-            a.h0 = c->d.h[b];
-            a.hu0 = c->d.hu[b];
-            a.hv0 = c->d.hv[b];
-            a.h1 = c->d.h[b ^ 1];
-            a.hu1 = c->d.hu[b ^ 1];
-            a.hv1 = c->d.hv[b ^ 1];
-            a.cur = c->cur_slot;
-            a.step_index = c->step_index;
-            hipError_t e = swe::launch_step(a, m.block_cells, threads,
-                                            c->params.load_schedule,
-                                            c->stream);
-            if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
-            c->cur_buf ^= 1;
-            c->cur_slot = (c->cur_slot + 1) % 3;
-            ++c->step_index;
+    for (int64_t k = 0; k < n; ++k) {
+        const int b = c->cur_buf;
+        a.h0 = c->d.h[b];
+        a.hu0 = c->d.hu[b];
+        a.hv0 = c->d.hv[b];
+        a.h1 = c->d.h[b ^ 1];
+        a.hu1 = c->d.hu[b ^ 1];
+        a.hv1 = c->d.hv[b ^ 1];
+        a.cur = c->cur_slot;
+        a.step_index = c->step_index;
+        if (dt_fixed) {
+            // dt = min(cfl * min R/s, dt_max) = dt_fixed[k] exactly
+            a.cfl = INFINITY;
+            a.dt_max = dt_fixed[k];
+            a.t_end = INFINITY;
         }
-        return SWE_OK;
-    };
+        hipError_t e = launch_step(a, m.block_cells, threads,
+                                   c->params.load_schedule, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
+        if (dt_log)
+            HIPCHK(c, hipMemcpyAsync(dt_log + k, &c->d.clock->last_dt, 8,
+                                     hipMemcpyDeviceToDevice, c->stream));
+        c->cur_buf ^= 1;
+        c->cur_slot = (c->cur_slot + 1) % 3;
+        ++c->step_index;
+    }
+    c->t_known = false;
+    return SWE_OK;
+}
+
+}  // namespace swe
+
+extern "C" {
+
+swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
+                       int64_t *steps_done, double *t_now)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    if (max_steps < 0) return fail(c, SWE_EINVAL, "max_steps < 0");
+    if (std::isnan(t_end)) return fail(c, SWE_EINVAL, "t_end is NaN");
+    if ((st = prepare(c))) return st;
+    Clock ck;
+    if (!c->t_known) {
+        if ((st = read_clock(c, &ck))) return st;
+    }
+    const int64_t steps0 = c->step_host;
+    swe::StepArgs a = swe::ctx_step_args(c, t_end);
     if (std::isinf(t_end) && t_end > 0) {
-        if ((st = launch_n(max_steps))) return st;
-        c->t_known = false;
-        done = max_steps;
+        if ((st = swe::ctx_enqueue(c, a, max_steps, nullptr, nullptr)))
+            return st;
         c->step_host = steps0 + max_steps;
         if (t_now) {
             if ((st = read_clock(c, &ck))) return st;
             *t_now = c->t_host;
         }
-        if (steps_done) *steps_done = done;
+        if (steps_done) *steps_done = max_steps;
         return SWE_OK;
     }
     int64_t launched = 0;
     while (launched < max_steps && c->t_host < t_end) {
         const int64_t n = std::min<int64_t>(c->params.check_every,
                                             max_steps - launched);
-        if ((st = launch_n(n))) return st;
+        if ((st = swe::ctx_enqueue(c, a, n, nullptr, nullptr))) return st;
         launched += n;
         if ((st = read_clock(c, &ck))) return st;
     }
-    done = c->step_host - steps0;
-    if (steps_done) *steps_done = done;
+    if (steps_done) *steps_done = c->step_host - steps0;
     if (t_now) *t_now = c->t_host;
     return SWE_OK;
+}
+
+swe_status swe_advance_dt(swe_ctx *c, int64_t n, const double *dt,
+                          double *dt_out)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    if (n < 0) return fail(c, SWE_EINVAL, "negative step count");
+    if (n == 0) return SWE_OK;
+    if (dt)
+        for (int64_t k = 0; k < n; ++k)
+            if (!(dt[k] >= 0.0) || !std::isfinite(dt[k]))
+                return fail(c, SWE_EINVAL,
+                            "time step " + std::to_string(k) +
+                                " must be finite and >= 0");
+    if ((st = prepare(c))) return st;
+    if (!c->t_known) {
+        Clock ck;
+        if ((st = read_clock(c, &ck))) return st;
+    }
+    double *log = nullptr;
+    if (dt_out) {
+        if ((st = swe::ctx_dt_buffer(c, n))) return st;
+        log = c->dt_dev;
+    }
+    swe::StepArgs a = swe::ctx_step_args(c, INFINITY);
+    if ((st = swe::ctx_enqueue(c, a, n, dt, log))) return st;
+    if (dt_out)
+        HIPCHK(c, hipMemcpyAsync(dt_out, log, size_t(n) * 8,
+                                 hipMemcpyDeviceToHost, c->stream));
+    Clock ck;
+    return read_clock(c, &ck);
 }
 
 swe_status swe_get_diagnostics(swe_ctx *c, double *mass, double *ledger,

@@ -69,5 +69,24 @@ struct swe_ctx {
     bool uploaded = false;     // host memory queued on the stream
     bool quiet_dirty = true;   // state buffers written outside a step
     bool mon_dirty = true;     // monitors to be reset before the next step
+    double *dt_dev = nullptr;  // time-step schedule (library-allocated)
+    int64_t dt_cap = 0;
 };
+
+namespace swe {
+
+// Internal steps shared by the C interface and the adjoint.
+swe_status ctx_prepare(swe_ctx *c);
+swe_status ctx_fail(swe_ctx *c, swe_status st, const std::string &msg);
+swe_status ctx_read_clock(swe_ctx *c);
+StepArgs ctx_step_args(swe_ctx *c, double t_end);
+// Enqueues n steps; advances the buffers, clock slot and step index. With
+// dt_fixed (host, n values) step k takes dt_fixed[k] as its time step;
+// with dt_log (device, n values) the time step of step k is copied there.
+swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
+                       const double *dt_fixed, double *dt_log);
+// Device buffer of at least n time steps in c->dt_dev.
+swe_status ctx_dt_buffer(swe_ctx *c, int64_t n);
+
+}  // namespace swe
 

@@ -130,6 +130,8 @@ def load():
     L.swe_get_time.argtypes = [_p, _pd, _pd, _pi64]
     L.swe_advance.restype = st
     L.swe_advance.argtypes = [_p, C.c_int64, C.c_double, _pi64, _pd]
+    L.swe_advance_dt.restype = st
+    L.swe_advance_dt.argtypes = [_p, C.c_int64, _pd, _pd]
     L.swe_get_diagnostics.restype = st
     L.swe_get_diagnostics.argtypes = [_p, _pd, _pd, _pi64]
     L.swe_reset_monitors.restype = st
@@ -352,6 +354,19 @@ def swe_advance(ctx, max_steps, t_end=math.inf, want_time=False):
                                    C.byref(done),
                                    C.byref(t) if sync else None))
     return done.value, (t.value if sync else None)
+
+
+def swe_advance_dt(ctx, n, dt=None, record=False):
+    """n steps with the given time steps (array of n) or, with dt None, the
+    CFL time steps; returns the time steps taken if record."""
+    d = None if dt is None else np.ascontiguousarray(dt, dtype=np.float64)
+    if d is not None and d.size != n:
+        raise ValueError("need one time step per step")
+    out = np.empty(n) if record else None
+    _check(ctx, load().swe_advance_dt(
+        ctx, int(n), None if d is None else d.ctypes.data_as(_pd),
+        None if out is None else out.ctypes.data_as(_pd)))
+    return out
 
 
 def swe_get_diagnostics(ctx):

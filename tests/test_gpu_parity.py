@@ -309,3 +309,25 @@ def test_monitors_closed_canal_reset_and_off():
     t = s.time()[0]
     assert np.array_equal(hm2, h)
     assert np.array_equal(tw2, np.where(h > case.h_dry, t, np.inf))
+
+
+def test_recorded_time_steps_replay_bitwise():
+    """A run's time steps, recorded and passed back as a frozen schedule,
+    reproduce it bit for bit; the frozen schedule also holds for a changed
+    input (the finite-difference checks of the adjoint rely on it)."""
+    from paper_2010_14416_amd import swe as S
+    case = W.bumps_canal(nx=90, ny=31, lx=30.0, ly=10.0, x_dam=15.0)
+    a = solver(case)
+    dts = S.swe_advance_dt(a.ctx, 40, None, record=True)
+    ref = solver(case)
+    ref.advance(40)
+    b = solver(case)
+    S.swe_advance_dt(b.ctx, 40, dts)
+    for x, y, w in zip(a.state(), ref.state(), b.state()):
+        assert np.array_equal(x, y) and np.array_equal(x, w)
+    assert np.all(dts > 0) and len(set(dts.tolist())) > 1
+    p = case.copy()
+    p.manning = case.manning * 1.01
+    c = solver(p)
+    got = S.swe_advance_dt(c.ctx, 40, dts, record=True)
+    assert np.array_equal(got, dts)
