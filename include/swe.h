@@ -216,6 +216,27 @@ swe_status swe_advance(swe_ctx *ctx, int64_t max_steps, double t_end,
 swe_status swe_advance_dt(swe_ctx *ctx, int64_t n, const double *dt,
                           double *dt_out);
 
+/* Discrete adjoint of a gauge misfit, for inverse analysis (calibrating
+ * friction and bed against observed depths). From the current state, runs
+ * `steps` ordinary steps (time steps recorded), evaluates
+ *   *loss = sum over k of (h(gauges[k]) - h_target[k])^2
+ * at the end, and returns its gradients with respect to the Manning
+ * coefficient and the bed elevation of every cell (user order, host arrays
+ * of n_cells; either may be NULL), with the time-step schedule of the run
+ * held fixed. The reverse sweep restores states from checkpoints taken
+ * every `checkpoint_every` steps (0: ceil(sqrt(steps))) and replays each
+ * segment with its recorded time steps. The derivative is that of the
+ * branches the forward run takes (wet/dry, wave-speed cases, star region,
+ * reconstruction maximum, positivity fix). Afterwards the context holds the
+ * final state, time and ledger of the forward run; monitors are reset.
+ * Needs block_cells = 256; allocates its scratch (about
+ * (2 checkpoint_every + steps / checkpoint_every) x 24 B per cell) for the
+ * call. Synchronises the stream. */
+swe_status swe_adjoint_gauges(swe_ctx *ctx, int64_t steps, int32_t n_gauges,
+                              const int32_t *gauges, const double *h_target,
+                              int32_t checkpoint_every, double *loss,
+                              double *grad_manning, double *grad_z);
+
 /* Total water volume sum |Omega_i| h_i [m^3], the volume added by the
  * positivity fix since the mesh was set [m^3], and the number of cells
  * with h > h_dry. Synchronises the stream. */

@@ -43,11 +43,12 @@ def build(verbose: bool = True) -> str:
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src in ["swe_kernels.hip"]:
+    for src in ["swe_kernels.hip", "swe_adjoint.hip"]:
         obj = os.path.join(BUILD, src + ".o")
         _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    for src in ["swe_mesh.cpp", "swe_api.cpp", "swe_ensemble.cpp"]:
+    for src in ["swe_mesh.cpp", "swe_api.cpp", "swe_ensemble.cpp",
+                "swe_adjoint.cpp"]:
         obj = os.path.join(BUILD, src + ".o")
         _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

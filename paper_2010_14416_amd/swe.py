@@ -132,6 +132,9 @@ def load():
     L.swe_advance.argtypes = [_p, C.c_int64, C.c_double, _pi64, _pd]
     L.swe_advance_dt.restype = st
     L.swe_advance_dt.argtypes = [_p, C.c_int64, _pd, _pd]
+    L.swe_adjoint_gauges.restype = st
+    L.swe_adjoint_gauges.argtypes = [_p, C.c_int64, C.c_int32, _pi32, _pd,
+                                     C.c_int32, _pd, _pd, _pd]
     L.swe_get_diagnostics.restype = st
     L.swe_get_diagnostics.argtypes = [_p, _pd, _pd, _pi64]
     L.swe_reset_monitors.restype = st
@@ -367,6 +370,23 @@ def swe_advance_dt(ctx, n, dt=None, record=False):
         ctx, int(n), None if d is None else d.ctypes.data_as(_pd),
         None if out is None else out.ctypes.data_as(_pd)))
     return out
+
+
+def swe_adjoint_gauges(ctx, steps, gauges, h_target, checkpoint_every=0):
+    """(loss, dL/dManning, dL/dz) of the gauge misfit after `steps` steps
+    from the current state, with the run's time steps held fixed."""
+    g = np.ascontiguousarray(gauges, dtype=np.int32)
+    t = np.ascontiguousarray(h_target, dtype=np.float64)
+    if g.size != t.size:
+        raise ValueError("one target per gauge")
+    n = _n_cells(ctx)
+    gm, gz = np.empty(n), np.empty(n)
+    loss = C.c_double()
+    _check(ctx, load().swe_adjoint_gauges(
+        ctx, int(steps), int(g.size), g.ctypes.data_as(_pi32),
+        t.ctypes.data_as(_pd), int(checkpoint_every), C.byref(loss),
+        gm.ctypes.data_as(_pd), gz.ctypes.data_as(_pd)))
+    return loss.value, gm, gz
 
 
 def swe_get_diagnostics(ctx):

@@ -1,0 +1,125 @@
+"""Discrete adjoint on the GPU (swe_adjoint_gauges): gradients of the gauge
+misfit against the adjoint oracle (PyTorch CPU autograd of the oracle's
+step) and against central differences of the GPU's own frozen-schedule
+runs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle import adjoint as A
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def solver(case, **kw):
+    from paper_2010_14416_amd import Solver
+    return Solver(case, device=0, **kw)
+
+
+def problem(case, steps, n_gauges=64, seed=5):
+    """Gauges on wet cells and the depths of a run with a perturbed Manning
+    field (both seeded), with the CFL schedule of the unperturbed run."""
+    from paper_2010_14416_amd import swe as S
+    rng = np.random.default_rng(seed)
+    wet = np.flatnonzero(case.h > 0.05)
+    gauges = rng.choice(wet, size=min(n_gauges, wet.size), replace=False)
+    s = solver(case)
+    dts = S.swe_advance_dt(s.ctx, steps, None, record=True)
+    tgt = case.copy()
+    tgt.manning = case.manning * (1.0 + 0.2 * rng.uniform(-1, 1,
+                                                          case.n_cells))
+    t = solver(tgt)
+    S.swe_advance_dt(t.ctx, steps, dts)
+    return gauges, t.state()[0][gauges], dts
+
+
+def gpu_loss(case, dts, gauges, target, manning=None, z=None):
+    from paper_2010_14416_amd import swe as S
+    c = case.copy()
+    if manning is not None:
+        c.manning = manning
+    if z is not None:
+        c.z = z
+    s = solver(c)
+    S.swe_advance_dt(s.ctx, len(dts), dts)
+    h = s.state()[0]
+    return float(np.sum((h[gauges] - target) ** 2))
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("name", ["bumps", "river"])
+def test_adjoint_matches_the_oracle(name):
+    from paper_2010_14416_amd import swe as S
+    case = (W.bumps_canal(nx=40, ny=14, lx=30.0, ly=10.0, x_dam=15.0)
+            if name == "bumps" else W.river(n_target=6_000, workers=1))
+    steps = 30
+    gauges, target, dts = problem(case, steps)
+    s = solver(case)
+    loss, gm, gz = S.swe_adjoint_gauges(s.ctx, steps, gauges, target,
+                                        checkpoint_every=7)
+    lo, gmo, gzo = A.gauge_misfit(case, dts, gauges, target)
+    say(f"[adjoint] {name}: loss gpu={loss!r} ora={lo!r} "
+        f"rel Linf dL/dm={rel(gm, gmo):.2e} dL/dz={rel(gz, gzo):.2e}")
+    assert abs(loss - lo) <= 1e-9 * lo
+    assert rel(gm, gmo) <= 1e-7
+    assert rel(gz, gzo) <= 1e-7
+    # the context ends at the forward's final state and time
+    ref = solver(case)
+    S.swe_advance_dt(ref.ctx, steps, dts)
+    for x, y in zip(s.state(), ref.state()):
+        assert np.array_equal(x, y)
+    assert s.time()[0] == ref.time()[0]
+
+
+def test_checkpoint_interval_does_not_change_bits():
+    from paper_2010_14416_amd import swe as S
+    case = W.bumps_canal(nx=40, ny=14, lx=30.0, ly=10.0, x_dam=15.0)
+    gauges, target, dts = problem(case, 25)
+    out = []
+    for k in (0, 1, 4, 25):
+        s = solver(case)
+        out.append(S.swe_adjoint_gauges(s.ctx, 25, gauges, target,
+                                        checkpoint_every=k))
+    for loss, gm, gz in out[1:]:
+        assert loss == out[0][0]
+        assert np.array_equal(gm, out[0][1]) and np.array_equal(gz, out[0][2])
+
+
+def test_manning_gradient_matches_central_differences():
+    """Smooth seeded directions on the wet cells; the GPU's frozen-schedule
+    runs give the differences."""
+    from paper_2010_14416_amd import swe as S
+    case = W.river(n_target=20_000, workers=1)
+    steps = 60
+    gauges, target, dts = problem(case, steps)
+    s = solver(case)
+    loss, gm, gz = S.swe_adjoint_gauges(s.ctx, steps, gauges, target)
+    rng = np.random.default_rng(11)
+    c = case.xy[case.tri].mean(axis=1)
+    x = (c - c.min(axis=0)) / (c.max(axis=0) - c.min(axis=0))
+    wet = case.h > 0.1
+    errs = []
+    for _ in range(4):
+        kx, ky = rng.integers(1, 4, 2)
+        d = np.sin(2 * np.pi * kx * x[:, 0] + rng.uniform(0, 6)) * np.cos(
+            2 * np.pi * ky * x[:, 1] + rng.uniform(0, 6)) * wet
+        eps = 1e-6
+        fd = (gpu_loss(case, dts, gauges, target, manning=case.manning +
+                       eps * d) -
+              gpu_loss(case, dts, gauges, target, manning=case.manning -
+                       eps * d)) / (2 * eps)
+        errs.append(abs(float(np.dot(gm, d)) - fd) / max(abs(fd),
+                                                         1e-3 * loss))
+    say(f"[adjoint fd] relative errors {errs}")
+    assert max(errs) <= 1e-6
