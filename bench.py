@@ -180,7 +180,8 @@ def main():
                     help="timed steps (1000; 500 for the ensemble)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="river",
-                    choices=["river", "bumps", "canal", "ensemble"])
+                    choices=["river", "bumps", "canal", "ensemble",
+                             "adjoint"])
     ap.add_argument("--cells", type=int, default=13_000_000)
     ap.add_argument("--block-cells", type=int, default=256)
     ap.add_argument("--block-threads", type=int, default=0,
@@ -207,10 +208,13 @@ def main():
                     help="ensemble members (--workload ensemble)")
     ap.add_argument("--solo-sample", type=int, default=16,
                     help="ensemble members also timed one at a time")
+    ap.add_argument("--fd-directions", type=int, default=32,
+                    help="finite-difference checks of the adjoint")
 
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = 500 if args.workload == "ensemble" else 1000
+        args.steps = {"ensemble": 500, "adjoint": 2000}.get(args.workload,
+                                                            1000)
 
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_mb,
@@ -228,6 +232,9 @@ def main():
 
     if args.workload == "ensemble":
         run_ensemble(args)
+        return
+    if args.workload == "adjoint":
+        run_adjoint(args)
         return
     t0 = time.perf_counter()
     case, desc = make_case(args)
@@ -401,6 +408,110 @@ def run_ensemble(args):
                       ensemble_ms=ens_ms,
                       speedup_vs_one_at_a_time=solo_total_ms / ens_ms),
         cpu_baseline=None)
+    print(json.dumps(out), flush=True)
+
+
+def run_adjoint(args):
+    """Inverse case on the 1 M-cell bumps canal: gradient of the squared
+    depth misfit at 64 seeded gauge cells after `steps` steps against a
+    seeded target run (Manning perturbed), w.r.t. per-cell Manning and bed,
+    time steps frozen from the forward run, sqrt(steps) checkpoints. Reports
+    the adjoint's time per step against the forward's and the relative
+    error against central differences of frozen-schedule runs on
+    seeded smooth directions."""
+    import torch
+    import workloads as W
+    from paper_2010_14416_amd import Solver, swe as S
+
+    case = W.bumps_canal()
+    steps = args.steps
+    rng = np.random.default_rng(np.random.SeedSequence(5))
+    wet = np.flatnonzero(case.h > 0.05)
+    gauges = rng.choice(wet, size=64, replace=False)
+    s = Solver(case, device=0)
+    dts = S.swe_advance_dt(s.ctx, steps, None, record=True)
+    tgt = case.copy()
+    tgt.manning = case.manning * (1.0 + 0.2 * rng.uniform(-1, 1,
+                                                          case.n_cells))
+    t = Solver(tgt, device=0)
+    S.swe_advance_dt(t.ctx, steps, dts)
+    target = t.state()[0][gauges]
+    t.close()
+
+    def forward_loss(manning=None, z=None):
+        c = case.copy()
+        if manning is not None:
+            c.manning = manning
+        if z is not None:
+            c.z = z
+        f = Solver(c, device=0)
+        S.swe_advance_dt(f.ctx, steps, dts)
+        h = f.state()[0]
+        f.close()
+        return float(np.sum((h[gauges] - target) ** 2))
+
+    # forward time per step with the frozen schedule (as in the FD runs)
+    f = Solver(case, device=0)
+    S.swe_advance_dt(f.ctx, 20, dts[:20])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.swe_advance_dt(f.ctx, steps, dts)
+    fwd_s = time.perf_counter() - t0
+    f.close()
+    a = Solver(case, device=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss, gm, gz = S.swe_adjoint_gauges(a.ctx, steps, gauges, target)
+    adj_s = time.perf_counter() - t0
+    a.close()
+    log(f"adjoint: loss {loss:.6e}; forward {fwd_s * 1e3:.1f} ms, "
+        f"forward + reverse {adj_s * 1e3:.1f} ms for {steps} steps")
+    # central differences on smooth directions (wet cells for Manning)
+    c = case.xy[case.tri].mean(axis=1)
+    x = (c - c.min(axis=0)) / (c.max(axis=0) - c.min(axis=0))
+    wet_mask = case.h > 0.1
+    errs_m, errs_z = [], []
+    for k in range(args.fd_directions):
+        kx, ky = rng.integers(1, 4, 2)
+        d = np.sin(2 * np.pi * kx * x[:, 0] + rng.uniform(0, 6)) * np.cos(
+            2 * np.pi * ky * x[:, 1] + rng.uniform(0, 6))
+        which = "m" if k % 2 == 0 else "z"
+        eps = 1e-6
+        if which == "m":
+            dm = d * wet_mask
+            fd = (forward_loss(manning=case.manning + eps * dm) -
+                  forward_loss(manning=case.manning - eps * dm)) / (2 * eps)
+            ad = float(np.dot(gm, dm))
+            errs_m.append(abs(ad - fd) / max(abs(fd), 1e-3 * loss))
+        else:
+            fd = (forward_loss(z=case.z + eps * d) -
+                  forward_loss(z=case.z - eps * d)) / (2 * eps)
+            ad = float(np.dot(gz, d))
+            errs_z.append(abs(ad - fd) / max(abs(fd), 1e-3 * loss))
+    log(f"finite differences (eps 1e-6): Manning max rel error "
+        f"{max(errs_m):.2e} (median {np.median(errs_m):.2e}), bed max "
+        f"{max(errs_z):.2e} (median {np.median(errs_z):.2e})")
+    # cost of one adjoint step: (forward + reverse) minus the forward, per
+    # step, against a forward step
+    ratio = (adj_s - fwd_s) / fwd_s
+    out = dict(
+        metric=METRIC, value=case.n_cells * steps / adj_s,
+        unit="cell-updates/s", n_gpus=1, steps=steps, warmup=20,
+        ms_per_step=adj_s * 1e3 / steps, higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload="adjoint-bumps-canal-1M: gauge misfit at 64 "
+                    "cells vs a perturbed-Manning target run, gradients "
+                    "w.r.t. Manning and bed, frozen time steps, sqrt(N) "
+                    "checkpoints", n_cells=case.n_cells),
+        roofline=None, cpu_baseline=None,
+        adjoint=dict(loss=loss, forward_ms=fwd_s * 1e3,
+                     forward_and_reverse_ms=adj_s * 1e3,
+                     reverse_step_vs_forward_step=ratio,
+                     fd_directions=args.fd_directions, fd_eps=1e-6,
+                     fd_max_rel_error_manning=max(errs_m),
+                     fd_max_rel_error_bed=max(errs_z),
+                     fd_median_rel_error_manning=float(np.median(errs_m)),
+                     fd_median_rel_error_bed=float(np.median(errs_z))))
     print(json.dumps(out), flush=True)
 
 

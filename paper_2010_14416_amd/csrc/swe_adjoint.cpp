@@ -6,9 +6,9 @@
 // time step, with the state saved every K steps (K = checkpoint interval,
 // sqrt(steps) by default). Reverse: segment by segment from the last, the
 // state is restored from its checkpoint and the segment replayed with its
-// recorded time steps (bit for bit the forward states), keeping every
-// state of the segment; then the adjoint steps run backwards through them.
-// Memory: about 2 K + ceil(steps / K) states of 24 B per cell.
+// recorded time steps (bit for bit the forward states) straight into the
+// segment's state slots; then the adjoint steps run backwards through them.
+// Memory: about K + ceil(steps / K) states of 24 B per cell.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -181,24 +181,25 @@ extern "C" swe_status swe_adjoint_gauges(swe_ctx *c, int64_t steps,
     A.n_cells = int32_t(nc);
     A.n_blocks = c->mesh.n_blocks;
 
-    // reverse, segment by segment
+    // reverse, segment by segment: replay the segment from its checkpoint
+    // straight into the segment's state slots (slot 0 is the checkpoint),
+    // then run its reverse steps backwards
+    auto state_at = [&](int64_t s, int64_t j) {
+        return j == 0 ? ckpt + size_t(s) * n_state : seg + size_t(j) * n_state;
+    };
     for (int64_t s = nseg - 1; s >= 0; --s) {
         const int64_t m = std::min(K, steps - s * K);
-        if ((st = copy_state(c, ckpt + size_t(s) * n_state, true))) return st;
-        // the state buffers were written from outside a step
-        ADJCHK(c, swe::launch_fill_u32((unsigned *)c->d.quiet, 0u,
-                                       int64_t(nb), c->stream));
-        for (int64_t j = 0; j < m; ++j) {
-            if ((st = copy_state(c, seg + size_t(j) * n_state, false)))
-                return st;
-            if (j + 1 == m) break;   // the segment's last state suffices
-            swe::StepArgs a = swe::ctx_step_args(c, INFINITY);
-            if ((st = swe::ctx_enqueue(c, a, 1, &dts[size_t(s * K + j)],
-                                       nullptr)))
+        for (int64_t j = 0; j + 1 < m; ++j) {
+            const double *u = state_at(s, j);
+            double *w = state_at(s, j + 1);
+            const double *in[3] = {u, u + n, u + 2 * n};
+            double *const out[3] = {w, w + n, w + 2 * n};
+            if ((st = swe::ctx_step_between(c, in, out,
+                                            dts[size_t(s * K + j)])))
                 return st;
         }
         for (int64_t j = m - 1; j >= 0; --j) {
-            const double *u = seg + size_t(j) * n_state;
+            const double *u = state_at(s, j);
             A.h = u;
             A.hu = u + n;
             A.hv = u + 2 * n;

@@ -472,6 +472,17 @@ __global__ __launch_bounds__(NC) void adj_cell_kernel(AdjArgs a)
     const bool owner = tid < nc;
     const int i = c0 + tid;
     const double g = a.g, h_dry = a.h_dry;
+    // the block's records first (edges to other blocks come first in the
+    // list), then the neighbour of the first edge, as in the forward step
+    int32_t ea = 0, eb = 0, ea2 = 0, eb2 = 0;
+    if (tid < ne) {
+        ea = a.be_a[e0 + tid];
+        eb = a.be_b[e0 + tid];
+    }
+    if (tid + NC < ne) {
+        ea2 = a.be_a[e0 + tid + NC];
+        eb2 = a.be_b[e0 + tid + NC];
+    }
     if (owner) {
         const CellState s = cell_at(a, i);
         s_h[tid] = s.h;
@@ -479,17 +490,23 @@ __global__ __launch_bounds__(NC) void adj_cell_kernel(AdjArgs a)
         s_v[tid] = s.v;
         s_z[tid] = s.z;
     }
+    CellState X;
+    X.h = 0.0; X.u = 0.0; X.v = 0.0; X.z = 0.0;
+    {
+        const bool xa = uint32_t(ea) < kSideBoundary;
+        const bool xb = uint32_t(eb) < kSideBoundary;
+        if (tid < ne && (xa || xb)) X = cell_at(a, xa ? ea : eb);
+    }
     __syncthreads();
-    for (int k = tid; k < ne; k += NC) {
-        const Side pa = decode_side(a.be_a[e0 + k]);
-        const Side pb = decode_side(a.be_b[e0 + k]);
+    auto edge = [&](int k, int32_t va, int32_t vb, const CellState &Y) {
+        const Side pa = decode_side(va), pb = decode_side(vb);
         CellState Lc, Rc;
         Rc.h = 0.0; Rc.u = 0.0; Rc.v = 0.0; Rc.z = 0.0;
         if (pa.kind == 0) {
             Lc.h = s_h[pa.local]; Lc.u = s_u[pa.local];
             Lc.v = s_v[pa.local]; Lc.z = s_z[pa.local];
         } else {
-            Lc = cell_at(a, pa.global);
+            Lc = Y;
         }
         BcEntry bc{};
         bool idle;
@@ -501,7 +518,7 @@ __global__ __launch_bounds__(NC) void adj_cell_kernel(AdjArgs a)
                 Rc.h = s_h[pb.local]; Rc.u = s_u[pb.local];
                 Rc.v = s_v[pb.local]; Rc.z = s_z[pb.local];
             } else {
-                Rc = cell_at(a, pb.global);
+                Rc = Y;
             }
             idle = Lc.h == 0.0 && Rc.h == 0.0;
         }
@@ -523,6 +540,19 @@ __global__ __launch_bounds__(NC) void adj_cell_kernel(AdjArgs a)
             d[3 * NC] = cr1;
             d[6 * NC] = cr2;
         }
+    };
+    if (tid < ne) edge(tid, ea, eb, X);
+    for (int k = tid + NC; k < ne; k += NC) {
+        int32_t va = ea2, vb = eb2;
+        if (k != tid + NC) {
+            va = a.be_a[e0 + k];
+            vb = a.be_b[e0 + k];
+        }
+        CellState Y;
+        Y.h = 0.0; Y.u = 0.0; Y.v = 0.0; Y.z = 0.0;
+        if (uint32_t(va) < kSideBoundary) Y = cell_at(a, va);
+        if (uint32_t(vb) < kSideBoundary) Y = cell_at(a, vb);
+        edge(k, va, vb, Y);
     }
     __syncthreads();
     if (!owner) return;

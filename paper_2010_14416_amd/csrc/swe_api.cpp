@@ -703,6 +703,33 @@ StepArgs ctx_step_args(swe_ctx *c, double t_end)
     return a;
 }
 
+swe_status ctx_step_between(swe_ctx *c, const double *const in[3],
+                            double *const out[3], double dt)
+{
+    StepArgs a = ctx_step_args(c, INFINITY);
+    a.h0 = in[0];
+    a.hu0 = in[1];
+    a.hv0 = in[2];
+    a.h1 = out[0];
+    a.hu1 = out[1];
+    a.hv1 = out[2];
+    a.cfl = INFINITY;   // dt = min(cfl * min R/s, dt_max) = dt exactly
+    a.dt_max = dt;
+    a.store_all = 1;    // `out` need not hold the state before `in`
+    a.cur = c->cur_slot;
+    a.step_index = c->step_index;
+    const int threads = c->params.block_threads == 0
+                            ? c->mesh.block_cells
+                            : c->params.block_threads;
+    hipError_t e = launch_step(a, c->mesh.block_cells, threads,
+                               c->params.load_schedule, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
+    c->cur_slot = (c->cur_slot + 1) % 3;
+    ++c->step_index;
+    c->t_known = false;
+    return SWE_OK;
+}
+
 swe_status ctx_dt_buffer(swe_ctx *c, int64_t n)
 {
     if (n <= c->dt_cap) return SWE_OK;
@@ -726,6 +753,7 @@ swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
     const int threads = c->params.block_threads == 0
                             ? m.block_cells
                             : c->params.block_threads;
+    int64_t logged = 0;   // dt_log entries written
     for (int64_t k = 0; k < n; ++k) {
         const int b = c->cur_buf;
         a.h0 = c->d.h[b];
@@ -745,9 +773,22 @@ swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
         hipError_t e = launch_step(a, m.block_cells, threads,
                                    c->params.load_schedule, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
-        if (dt_log)
-            HIPCHK(c, hipMemcpyAsync(dt_log + k, &c->d.clock->last_dt, 8,
-                                     hipMemcpyDeviceToDevice, c->stream));
+        // the clock keeps the time steps of the last 8 step indices: copy
+        // them out whenever the ring is about to wrap, and at the end
+        const long long q = c->step_index;
+        if (dt_log && (((q + 1) & 7) == 0 || k + 1 == n)) {
+            int64_t j = logged;
+            while (j <= k) {
+                const int slot = int((q - k + j) & 7);
+                const int64_t run = std::min<int64_t>(k - j + 1, 8 - slot);
+                HIPCHK(c, hipMemcpyAsync(dt_log + j,
+                                         &c->d.clock->dt_ring[slot],
+                                         size_t(run) * 8,
+                                         hipMemcpyDeviceToDevice, c->stream));
+                j += run;
+            }
+            logged = k + 1;
+        }
         c->cur_buf ^= 1;
         c->cur_slot = (c->cur_slot + 1) % 3;
         ++c->step_index;

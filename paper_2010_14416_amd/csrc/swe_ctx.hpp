@@ -85,6 +85,10 @@ StepArgs ctx_step_args(swe_ctx *c, double t_end);
 // with dt_log (device, n values) the time step of step k is copied there.
 swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
                        const double *dt_fixed, double *dt_log);
+// One step from the state arrays `in` (h, hu, hv) into `out`, outside the
+// context's ping-pong buffers, with time step dt (monitors not updated).
+swe_status ctx_step_between(swe_ctx *c, const double *const in[3],
+                            double *const out[3], double dt);
 // Device buffer of at least n time steps in c->dt_dev.
 swe_status ctx_dt_buffer(swe_ctx *c, int64_t n);
 

@@ -31,7 +31,8 @@ struct Clock {
     unsigned int health;           // bit 0: non-finite state, bit 1: dt = inf
     unsigned int pad;
     long long bad_step;            // first step index that raised health
-    long long pad2[9];
+    double dt_ring[8];             // time step of step index k at k mod 8
+    long long pad2;
     // bits of min over wet cells of R_i / s_i, per slot and lane
     unsigned long long minrs[3][kClockLanes][16];
 };

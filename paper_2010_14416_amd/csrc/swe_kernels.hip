@@ -120,6 +120,7 @@ __device__ __forceinline__ void block_finish(const StepArgs &a, int blk,
             const int nn = nxt == 2 ? 0 : nxt + 1;
             clock->t[nxt] = tn;
             clock->last_dt = dt;
+            clock->dt_ring[a.step_index & 7] = dt;
             if (dt > 0.0) clock->steps += 1;
             for (int x = 0; x < kClockLanes; ++x)
                 atomicExch(&clock->minrs[nn][x][0], kInfBits);
