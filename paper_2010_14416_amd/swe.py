@@ -646,3 +646,34 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+
+def gauge_misfit(solver, manning, z, state, steps, gauges, h_target,
+                 checkpoint_every=0):
+    """The gauge misfit after `steps` steps from `state` (h, hu, hv) at time
+    0, as a torch scalar differentiable with respect to the per-cell
+    Manning field and bed (float64 tensors in user cell order, host or
+    device): the forward run and the discrete adjoint run in
+    swe_adjoint_gauges, with the run's time steps held fixed."""
+    import torch
+
+    class _GaugeMisfit(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, m, zz):
+            swe_set_manning(solver.ctx, m.detach())
+            swe_set_bathymetry(solver.ctx, zz.detach())
+            swe_set_state(solver.ctx, *state)
+            swe_set_time(solver.ctx, 0.0, 0)
+            loss, gm, gz = swe_adjoint_gauges(solver.ctx, steps, gauges,
+                                              h_target, checkpoint_every)
+            ctx.save_for_backward(torch.from_numpy(gm).to(m.device),
+                                  torch.from_numpy(gz).to(zz.device))
+            return torch.tensor(loss, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, grad):
+            gm, gz = ctx.saved_tensors
+            g = grad.to(gm.device)
+            return g * gm, g * gz
+
+    return _GaugeMisfit.apply(manning, z)

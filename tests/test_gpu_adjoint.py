@@ -123,3 +123,31 @@ def test_manning_gradient_matches_central_differences():
                                                          1e-3 * loss))
     say(f"[adjoint fd] relative errors {errs}")
     assert max(errs) <= 1e-6
+
+
+def test_autograd_function_and_a_descent_step():
+    """The torch.autograd wrapper returns the adjoint's gradients, and a
+    step against them lowers the misfit (inverse analysis of Manning)."""
+    import torch
+    from paper_2010_14416_amd import swe as S
+    case = W.river(n_target=6_000, workers=1)
+    steps = 40
+    gauges, target, _ = problem(case, steps)
+    s = solver(case)
+    state = (case.h, case.hu, case.hv)
+    m = torch.tensor(case.manning, dtype=torch.float64, requires_grad=True)
+    z = torch.tensor(case.z, dtype=torch.float64, requires_grad=True)
+    loss = S.gauge_misfit(s, m, z, state, steps, gauges, target)
+    loss.backward()
+    d = solver(case)
+    l2, gm, gz = S.swe_adjoint_gauges(d.ctx, steps, gauges, target)
+    assert loss.item() == l2
+    assert np.array_equal(m.grad.numpy(), gm)
+    assert np.array_equal(z.grad.numpy(), gz)
+    with torch.no_grad():
+        m2 = m - 1e-3 * m.grad / m.grad.abs().max() * m.abs().max()
+    loss2 = S.gauge_misfit(s, m2.clone().requires_grad_(),
+                           z.detach().clone().requires_grad_(), state, steps,
+                           gauges, target)
+    say(f"[inverse] misfit {loss.item()!r} -> {loss2.item()!r}")
+    assert loss2.item() < loss.item()
