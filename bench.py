@@ -37,8 +37,9 @@ PEAK_HBM_GBS = 8000.0           # MI355X HBM3E, published
 # out, per-cell bed / friction / 1/area / inscribed radius, ~1.5 edges of
 # geometry and connectivity, per-cell edge slots); derivation in the design doc.
 ALG_BYTES_PER_CELL = 140
-KERNEL_SRC = os.path.join(ROOT, "paper_2010_14416_amd", "csrc",
-                          "swe_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2010_14416_amd", "csrc", f)
+              for f in ("swe_kernels.hip", "swe_scheme.hpp", "swe_device.hpp",
+                        "swe_mesh.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 
 
@@ -47,8 +48,12 @@ def log(msg):
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """Hash of the sources the step kernel is compiled from."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def make_case(args):
