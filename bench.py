@@ -420,10 +420,12 @@ def run_adjoint(args):
     """Inverse case on the 1 M-cell bumps canal: gradient of the squared
     depth misfit at 64 seeded gauge cells after `steps` steps against a
     seeded target run (Manning perturbed), w.r.t. per-cell Manning and bed,
-    time steps frozen from the forward run, sqrt(steps) checkpoints. Reports
-    the adjoint's time per step against the forward's and the relative
-    error against central differences of frozen-schedule runs on
-    seeded smooth directions."""
+    time steps frozen from the forward run. Timed twice: with the interval
+    the library picks (every state kept in HBM when it fits, no replay) and
+    with checkpoints every ceil(sqrt(steps)) steps (least memory). Reports
+    the adjoint's time per step against the forward's, and the relative
+    error against central differences of frozen-schedule runs on seeded
+    smooth directions."""
     import torch
     import workloads as W
     from paper_2010_14416_amd import Solver, swe as S
@@ -463,14 +465,27 @@ def run_adjoint(args):
     S.swe_advance_dt(f.ctx, steps, dts)
     fwd_s = time.perf_counter() - t0
     f.close()
-    a = Solver(case, device=0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    loss, gm, gz = S.swe_adjoint_gauges(a.ctx, steps, gauges, target)
-    adj_s = time.perf_counter() - t0
-    a.close()
+    def adjoint(every):
+        a = Solver(case, device=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = S.swe_adjoint_gauges(a.ctx, steps, gauges, target,
+                                   checkpoint_every=every)
+        el = time.perf_counter() - t0
+        a.close()
+        return res, el
+
+    k_sqrt = int(math.ceil(math.sqrt(steps)))
+    (loss, gm, gz), adj_s = adjoint(0)
+    (loss2, gm2, gz2), adj_sqrt_s = adjoint(k_sqrt)
+    same = (loss2 == loss and np.array_equal(gm2, gm) and
+            np.array_equal(gz2, gz))
     log(f"adjoint: loss {loss:.6e}; forward {fwd_s * 1e3:.1f} ms, "
-        f"forward + reverse {adj_s * 1e3:.1f} ms for {steps} steps")
+        f"forward + reverse {adj_s * 1e3:.1f} ms for {steps} steps "
+        f"(states kept), {adj_sqrt_s * 1e3:.1f} ms with checkpoints every "
+        f"{k_sqrt}; same bits: {same}")
+    if not same:
+        raise SystemExit("the checkpoint interval changed the gradients")
     # central differences on smooth directions (wet cells for Manning)
     c = case.xy[case.tri].mean(axis=1)
     x = (c - c.min(axis=0)) / (c.max(axis=0) - c.min(axis=0))
@@ -499,6 +514,7 @@ def run_adjoint(args):
     # cost of one adjoint step: (forward + reverse) minus the forward, per
     # step, against a forward step
     ratio = (adj_s - fwd_s) / fwd_s
+    ratio_sqrt = (adj_sqrt_s - fwd_s) / fwd_s
     out = dict(
         metric=METRIC, value=case.n_cells * steps / adj_s,
         unit="cell-updates/s", n_gpus=1, steps=steps, warmup=20,
@@ -506,12 +522,15 @@ def run_adjoint(args):
         scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
         config=dict(workload="adjoint-bumps-canal-1M: gauge misfit at 64 "
                     "cells vs a perturbed-Manning target run, gradients "
-                    "w.r.t. Manning and bed, frozen time steps, sqrt(N) "
-                    "checkpoints", n_cells=case.n_cells),
+                    "w.r.t. Manning and bed, frozen time steps, states "
+                    "kept in HBM", n_cells=case.n_cells),
         roofline=None, cpu_baseline=None,
         adjoint=dict(loss=loss, forward_ms=fwd_s * 1e3,
                      forward_and_reverse_ms=adj_s * 1e3,
                      reverse_step_vs_forward_step=ratio,
+                     sqrt_checkpoints_every=k_sqrt,
+                     forward_and_reverse_sqrt_checkpoints_ms=adj_sqrt_s * 1e3,
+                     reverse_step_vs_forward_step_sqrt_checkpoints=ratio_sqrt,
                      fd_directions=args.fd_directions, fd_eps=1e-6,
                      fd_max_rel_error_manning=max(errs_m),
                      fd_max_rel_error_bed=max(errs_z),

@@ -224,14 +224,17 @@ swe_status swe_advance_dt(swe_ctx *ctx, int64_t n, const double *dt,
  * coefficient and the bed elevation of every cell (user order, host arrays
  * of n_cells; either may be NULL), with the time-step schedule of the run
  * held fixed. The reverse sweep restores states from checkpoints taken
- * every `checkpoint_every` steps (0: ceil(sqrt(steps))) and replays each
- * segment with its recorded time steps. The derivative is that of the
+ * every K = `checkpoint_every` steps and replays each segment with its
+ * recorded time steps; K = 1 keeps every state and replays nothing. With
+ * checkpoint_every = 0 the library picks the smallest K whose states fit in
+ * half the free device memory, and at most ceil(sqrt(steps)) (the least
+ * memory). Any K gives the same bits. The derivative is that of the
  * branches the forward run takes (wet/dry, wave-speed cases, star region,
  * reconstruction maximum, positivity fix). Afterwards the context holds the
  * final state, time and ledger of the forward run; monitors are reset.
- * Needs block_cells = 256; allocates its scratch (about
- * (2 checkpoint_every + steps / checkpoint_every) x 24 B per cell) for the
- * call. Synchronises the stream. */
+ * Needs block_cells = 256; allocates its scratch for the call: about
+ * (K + steps / K + 5) x 24 B per cell for K > 1, (steps + 6) x 24 B per
+ * cell for K = 1. Synchronises the stream. */
 swe_status swe_adjoint_gauges(swe_ctx *ctx, int64_t steps, int32_t n_gauges,
                               const int32_t *gauges, const double *h_target,
                               int32_t checkpoint_every, double *loss,

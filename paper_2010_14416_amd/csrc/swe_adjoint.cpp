@@ -3,12 +3,16 @@
 // the model match observed depths.
 //
 // Forward: `steps` ordinary steps from the context's state, recording each
-// time step, with the state saved every K steps (K = checkpoint interval,
-// sqrt(steps) by default). Reverse: segment by segment from the last, the
-// state is restored from its checkpoint and the segment replayed with its
-// recorded time steps (bit for bit the forward states) straight into the
-// segment's state slots; then the adjoint steps run backwards through them.
-// Memory: about K + ceil(steps / K) states of 24 B per cell.
+// time step, with the state saved every K steps (K = checkpoint interval).
+// Reverse: segment by segment from the last, the state is restored from its
+// checkpoint and the segment replayed with its recorded time steps (bit for
+// bit the forward states) straight into the segment's state slots; then the
+// adjoint steps run backwards through them. Memory: about K + ceil(steps / K)
+// states of 24 B per cell. K = 1 keeps every state: the forward steps write
+// straight into their slots and nothing is replayed. Unless the caller fixes
+// K, it is the smallest interval whose states fit in half the free device
+// memory (a mesh of a million cells keeps thousands of states in HBM), and at
+// most ceil(sqrt(steps)), which minimises the memory.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -56,6 +60,26 @@ swe_status copy_state(swe_ctx *c, double *dst, bool to_ctx)
     return SWE_OK;
 }
 
+// States held for interval K: every state when K = 1, else the
+// checkpoints, the slots of one segment and the final state.
+int64_t states_held(int64_t steps, int64_t K)
+{
+    return K == 1 ? steps + 1 : (steps + K - 1) / K + K + 1;
+}
+
+int64_t pick_interval(int64_t steps, size_t state_bytes, size_t other_bytes)
+{
+    const int64_t k_min_memory =
+        std::max<int64_t>(1, int64_t(std::ceil(std::sqrt(double(steps)))));
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return k_min_memory;
+    const double budget = 0.5 * double(free_b) - double(other_bytes);
+    for (int64_t K = 1; K < k_min_memory; ++K)
+        if (double(states_held(steps, K)) * double(state_bytes) <= budget)
+            return K;
+    return k_min_memory;
+}
+
 }  // namespace
 
 extern "C" swe_status swe_adjoint_gauges(swe_ctx *c, int64_t steps,
@@ -85,17 +109,15 @@ extern "C" swe_status swe_adjoint_gauges(swe_ctx *c, int64_t steps,
     if (st) return st;
     if (!c->t_known && (st = swe::ctx_read_clock(c))) return st;
 
+    const size_t n = size_t(nc), nb = size_t(c->mesh.n_blocks);
+    const size_t n_state = 3 * n;
+    // besides the states: adjoints, gradients, ledger copy
+    const size_t other = 2 * n_state + 2 * n_state + 3 * n + nb;
     const int64_t K = checkpoint_every > 0
                           ? std::min<int64_t>(checkpoint_every, steps)
-                          : std::max<int64_t>(
-                                1, int64_t(std::ceil(std::sqrt(double(steps)))));
+                          : pick_interval(steps, n_state * 8, other * 8);
     const int64_t nseg = (steps + K - 1) / K;
-    const size_t n = size_t(nc), nb = size_t(c->mesh.n_blocks);
-    // scratch: checkpoints, segment states, final state, adjoints, gradients,
-    // ledger copy
-    const size_t n_state = 3 * n;
-    const size_t doubles = size_t(nseg) * n_state + size_t(K) * n_state +
-                           n_state + 2 * n_state + 2 * n_state + 3 * n + nb;
+    const size_t doubles = size_t(states_held(steps, K)) * n_state + other;
     DeviceScratch scratch;
     {
         hipError_t e = hipMalloc(&scratch.p, doubles * 8);
@@ -106,8 +128,10 @@ extern "C" swe_status swe_adjoint_gauges(swe_ctx *c, int64_t steps,
                                 " bytes: " + hipGetErrorString(e));
     }
     double *p = (double *)scratch.p;
+    // with K = 1, ckpt holds the state before every step and final_state,
+    // right behind it, is the slot the last step writes
     double *ckpt = p;                    p += size_t(nseg) * n_state;
-    double *seg = p;                     p += size_t(K) * n_state;
+    double *seg = p;                     p += K > 1 ? size_t(K) * n_state : 0;
     double *final_state = p;             p += n_state;
     double *lam[2] = {p, p + n_state};   p += 2 * n_state;
     double *ld = p;                      p += n_state;
@@ -119,17 +143,26 @@ extern "C" swe_status swe_adjoint_gauges(swe_ctx *c, int64_t steps,
 
     // forward: ordinary steps, time steps recorded, checkpoints
     if ((st = swe::ctx_dt_buffer(c, steps))) return st;
-    for (int64_t s = 0; s < nseg; ++s) {
-        const int64_t m = std::min(K, steps - s * K);
-        if ((st = copy_state(c, ckpt + size_t(s) * n_state, false))) return st;
+    if (K == 1) {
+        if ((st = copy_state(c, ckpt, false))) return st;
         swe::StepArgs a = swe::ctx_step_args(c, INFINITY);
-        if ((st = swe::ctx_enqueue(c, a, m, nullptr, c->dt_dev + s * K)))
+        if ((st = swe::ctx_enqueue(c, a, steps, nullptr, c->dt_dev, ckpt,
+                                   n_state)))
             return st;
+    } else {
+        for (int64_t s = 0; s < nseg; ++s) {
+            const int64_t m = std::min(K, steps - s * K);
+            if ((st = copy_state(c, ckpt + size_t(s) * n_state, false)))
+                return st;
+            swe::StepArgs a = swe::ctx_step_args(c, INFINITY);
+            if ((st = swe::ctx_enqueue(c, a, m, nullptr, c->dt_dev + s * K)))
+                return st;
+        }
+        if ((st = copy_state(c, final_state, false))) return st;
     }
     std::vector<double> dts(static_cast<size_t>(steps));
     ADJCHK(c, hipMemcpyAsync(dts.data(), c->dt_dev, size_t(steps) * 8,
                              hipMemcpyDeviceToHost, c->stream));
-    if ((st = copy_state(c, final_state, false))) return st;
     if ((st = swe::ctx_read_clock(c))) return st;   // also checks health
     const double t_final = c->t_host;
     const int64_t steps_final = c->step_host;

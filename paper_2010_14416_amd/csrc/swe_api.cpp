@@ -716,6 +716,12 @@ swe_status ctx_step_between(swe_ctx *c, const double *const in[3],
     a.cfl = INFINITY;   // dt = min(cfl * min R/s, dt_max) = dt exactly
     a.dt_max = dt;
     a.store_all = 1;    // `out` need not hold the state before `in`
+    a.mon_rate = nullptr;
+    a.mon_vol = nullptr;
+    a.blk_bnd = nullptr;
+    a.blk_bnd_rec = nullptr;
+    a.h_max = nullptr;
+    a.t_wet = nullptr;
     a.cur = c->cur_slot;
     a.step_index = c->step_index;
     const int threads = c->params.block_threads == 0
@@ -747,21 +753,35 @@ swe_status ctx_dt_buffer(swe_ctx *c, int64_t n)
 }
 
 swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
-                       const double *dt_fixed, double *dt_log)
+                       const double *dt_fixed, double *dt_log,
+                       double *slots, size_t stride)
 {
     const BlockMesh &m = c->mesh;
+    const size_t nc = size_t(m.n_cells);
     const int threads = c->params.block_threads == 0
                             ? m.block_cells
                             : c->params.block_threads;
     int64_t logged = 0;   // dt_log entries written
     for (int64_t k = 0; k < n; ++k) {
-        const int b = c->cur_buf;
-        a.h0 = c->d.h[b];
-        a.hu0 = c->d.hu[b];
-        a.hv0 = c->d.hv[b];
-        a.h1 = c->d.h[b ^ 1];
-        a.hu1 = c->d.hu[b ^ 1];
-        a.hv1 = c->d.hv[b ^ 1];
+        if (slots) {
+            double *u = slots + size_t(k) * stride;
+            double *w = u + stride;
+            a.h0 = u;
+            a.hu0 = u + nc;
+            a.hv0 = u + 2 * nc;
+            a.h1 = w;
+            a.hu1 = w + nc;
+            a.hv1 = w + 2 * nc;
+            a.store_all = 1;   // a fresh slot holds no earlier state
+        } else {
+            const int b = c->cur_buf;
+            a.h0 = c->d.h[b];
+            a.hu0 = c->d.hu[b];
+            a.hv0 = c->d.hv[b];
+            a.h1 = c->d.h[b ^ 1];
+            a.hu1 = c->d.hu[b ^ 1];
+            a.hv1 = c->d.hv[b ^ 1];
+        }
         a.cur = c->cur_slot;
         a.step_index = c->step_index;
         if (dt_fixed) {
@@ -789,7 +809,7 @@ swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
             }
             logged = k + 1;
         }
-        c->cur_buf ^= 1;
+        if (!slots) c->cur_buf ^= 1;
         c->cur_slot = (c->cur_slot + 1) % 3;
         ++c->step_index;
     }

@@ -83,8 +83,12 @@ StepArgs ctx_step_args(swe_ctx *c, double t_end);
 // Enqueues n steps; advances the buffers, clock slot and step index. With
 // dt_fixed (host, n values) step k takes dt_fixed[k] as its time step;
 // with dt_log (device, n values) the time step of step k is copied there.
+// With slots, the steps run outside the ping-pong buffers: step k reads the
+// state at slots + k * stride (h, hu, hv, n_cells values each) and writes
+// every cell of slots + (k + 1) * stride.
 swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
-                       const double *dt_fixed, double *dt_log);
+                       const double *dt_fixed, double *dt_log,
+                       double *slots = nullptr, size_t stride = 0);
 // One step from the state arrays `in` (h, hu, hv) into `out`, outside the
 // context's ping-pong buffers, with time step dt (monitors not updated).
 swe_status ctx_step_between(swe_ctx *c, const double *const in[3],
