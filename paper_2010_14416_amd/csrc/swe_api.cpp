@@ -82,9 +82,8 @@ size_t layout(const BlockMesh &m, char *base, DevBufs *d)
     t.ledger = (double *)take(nb * 8);
     t.quiet = (int32_t *)take(nb * 4);
     t.mon_rate = (double *)take(nbnd * 8);
-    t.blk_bnd = (int32_t *)take((nb + 1) * 4);
-    t.blk_bnd_rec = (int32_t *)take(nb * 4);
     t.mon_vol = (double *)take(nbnd * 8);
+    t.blk_bnd = (int32_t *)take(nb * 16);
     t.h_max = (double *)take(nc * 8);
     t.t_wet = (double *)take(nc * 8);
     t.part_mass = (double *)take(kDiagParts * 8);
@@ -152,9 +151,6 @@ swe_status prepare(swe_ctx *c)
         if ((st = upload(c, d.blk_edge, m.blk_edge.data(), m.blk_edge.size())))
             return st;
         if ((st = upload(c, d.blk_bnd, m.blk_bnd.data(), m.blk_bnd.size())))
-            return st;
-        if ((st = upload(c, d.blk_bnd_rec, m.blk_bnd_rec.data(),
-                         m.blk_bnd_rec.size())))
             return st;
         const size_t nbe = m.be_a.size();
         if ((st = upload(c, d.be_a, m.be_a.data(), nbe))) return st;
@@ -688,7 +684,6 @@ StepArgs ctx_step_args(swe_ctx *c, double t_end)
         a.mon_rate = c->d.mon_rate;
         a.mon_vol = c->d.mon_vol;
         a.blk_bnd = c->d.blk_bnd;
-        a.blk_bnd_rec = c->d.blk_bnd_rec;
         a.h_max = c->d.h_max;
         a.t_wet = c->d.t_wet;
     }
@@ -719,7 +714,6 @@ swe_status ctx_step_between(swe_ctx *c, const double *const in[3],
     a.mon_rate = nullptr;
     a.mon_vol = nullptr;
     a.blk_bnd = nullptr;
-    a.blk_bnd_rec = nullptr;
     a.h_max = nullptr;
     a.t_wet = nullptr;
     a.cur = c->cur_slot;

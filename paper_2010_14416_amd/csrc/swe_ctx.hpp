@@ -26,7 +26,7 @@ struct DevBufs {
     double *ledger;
     int32_t *quiet;
     double *mon_rate, *mon_vol;   // per boundary slot
-    int32_t *blk_bnd, *blk_bnd_rec;
+    int32_t *blk_bnd;             // per block, 4 values
     double *h_max, *t_wet;        // per cell (internal order)
     double *part_mass;
     unsigned long long *part_wet;

@@ -66,8 +66,8 @@ struct StepArgs {
     // the highest depth and the first time with h > h_dry (+inf: never)
     double *mon_rate;
     double *mon_vol;
-    const int32_t *blk_bnd;       // per block: first boundary slot (+1 entry)
-    const int32_t *blk_bnd_rec;   // per block: record of its first slot
+    // per block 4 values {first slot, record of the first slot, slots, 0}
+    const int32_t *blk_bnd;
     double *h_max;
     double *t_wet;
     // ensembles (all null for one mesh): per block its member, with the

@@ -210,6 +210,7 @@ void swe_step_kernel(StepArgs a)
     __shared__ double red_min[NT / 64];
     __shared__ double red_sum[NT / 64];
     __shared__ unsigned red_bad[NT / 64];
+    __shared__ int4 s_bnd[1];
     double *s_h = lds;
     double *s_u = s_h + NC;
     double *s_v = s_u + NC;
@@ -242,6 +243,10 @@ void swe_step_kernel(StepArgs a)
 
     // phase 1: owned cell, first edge record (+ geometry), neighbour state
     const int quiet_steps = a.quiet[blk];
+    // the block's boundary slots (discharge monitors), to LDS with phase 1
+    int4 bnd = make_int4(0, 0, 0, 0);
+    if (MON && tid == NC / 64)
+        bnd = *reinterpret_cast<const int4 *>(a.blk_bnd + 4 * blk);
     double h = 0.0, hu = 0.0, hv = 0.0, zc = 0.0;
     if (tid < NC && tid < nc_read) {
         h = a.h0[i];
@@ -292,6 +297,7 @@ void swe_step_kernel(StepArgs a)
         }
     }
     const StepTime st = step_time(a, cw, t_end);
+    if (MON && tid == NC / 64) s_bnd[0] = bnd;
     if (owner) {
         s_h[tid] = h;
         s_z[tid] = zc;
@@ -399,6 +405,7 @@ void swe_step_kernel(StepArgs a)
     double rs = INFINITY, clamp = 0.0;
     unsigned bad = 0;
     bool active = owner;   // owned cell not on the quiet dry path
+    double hn = hc, hun = 0.0, hvn = 0.0;   // U^{n+1} of the owned cell
     if (owner) {
         double R0 = 0.0, R1 = 0.0, R2 = 0.0;
 #pragma unroll
@@ -407,7 +414,8 @@ void swe_step_kernel(StepArgs a)
             R1 += s_c[(3 + k) * NC + tid];
             R2 += s_c[(6 + k) * NC + tid];
         }
-        double hn = hc, hun = hu, hvn = hv;
+        hun = hu;
+        hvn = hv;
         const double dt = st.dt;
         if (dt > 0.0 && hc <= h_dry && R0 == 0.0 && R1 == 0.0 && R2 == 0.0) {
             // no friction below h_dry; h + dt*(+-0) cannot go negative
@@ -430,43 +438,47 @@ void swe_step_kernel(StepArgs a)
                 cell_update(h_dry, dt, area, hc > h_dry ? gm2 : 0.0, hc, hu,
                             hv, R0, R1, R2, hn, hun, hvn, clamp);
         }
-        // a quiet cell of a block quiet in the two previous steps already
-        // holds (h, 0, 0) in the output buffer (it held U^{n-1} = U^n)
-        if (active || quiet_steps < 2 || a.store_all) {
-            a.h1[i] = hn;
-            a.hu1[i] = hun;
-            a.hv1[i] = hvn;
-        }
-        if (MON && hn > hc) {
-            // flood envelope: the depth only rises where hn > h, and
-            // h_max >= h always holds
-            const double hm = a.h_max[i];
-            if (hn > hm) {
-                a.h_max[i] = hn;
-                if (hm <= h_dry && hn > h_dry) a.t_wet[i] = st.tn;
-            }
-        }
         if (!isfinite(hn) || !isfinite(hun) || !isfinite(hvn)) bad = 1u;
         if (hn > h_dry) {
             const double u = hun / hn, v = hvn / hn;
             rs = inr / (sqrt(g * hn) + sqrt(u * u + v * v));
         }
     }
-    if (MON) {
-        // discharge monitors: the volume leaving through each boundary edge
-        // per unit time, L G_1 = -(its mass contribution to its cell), read
-        // back from the cell's side slot
-        const int s0 = a.blk_bnd[blk], nbnd = a.blk_bnd[blk + 1] - s0;
-        for (int k = tid; k < nbnd; k += NT) {
-            const Side pa = decode_side(a.be_a[a.blk_bnd_rec[blk] + k]);
-            const double rate = -s_c[pa.k * NC + pa.local];
-            a.mon_rate[s0 + k] = rate;
-            a.mon_vol[s0 + k] += st.dt * rate;
-        }
-    }
     block_finish<NT>(a, blk, clock, first, rs, clamp, bad, active,
                      quiet_steps, st.unbounded, st.dt, st.tn,
                      a.cur == 2 ? 0 : a.cur + 1, red_min, red_sum, red_bad);
+    // the stores come last: no instruction after them waits for a load, so
+    // the wave never waits for its own stores. A quiet cell of a block quiet
+    // in the two previous steps already holds (h, 0, 0) in the output buffer
+    // (it held U^{n-1} = U^n).
+    if (owner && (active || quiet_steps < 2 || a.store_all)) {
+        a.h1[i] = hn;
+        a.hu1[i] = hun;
+        a.hv1[i] = hvn;
+    }
+    if (MON && owner && hn > hc) {
+        // flood envelope: h_max >= h always holds, so the highest depth can
+        // only change where the depth rose
+        const double hm = a.h_max[i];
+        if (hn > hm) {
+            a.h_max[i] = hn;
+            if (hm <= h_dry && hn > h_dry) a.t_wet[i] = st.tn;
+        }
+    }
+    if (MON && s_bnd[0].z > 0) {
+        // discharge monitors of the block's boundary slots: the volume
+        // leaving per unit time, L G_1 = -(the edge's mass contribution to
+        // its cell), read back from the cell's side slot. One edge per
+        // slot: the volume's single addition is the plain sum (an atomic
+        // only so that nothing waits for it).
+        const int4 b = s_bnd[0];
+        for (int k = tid; k < b.z; k += NT) {
+            const Side pa = decode_side(a.be_a[b.y + k]);
+            const double rate = -s_c[pa.k * NC + pa.local];
+            a.mon_rate[b.x + k] = rate;
+            unsafeAtomicAdd(&a.mon_vol[b.x + k], st.dt * rate);
+        }
+    }
 }
 
 __global__ void clock_set_kernel(Clock *c, double t, long long steps)

@@ -467,11 +467,12 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
         return false;
     }
     M.bnd_tag.resize(blk_bnd[nblk]);
-    M.blk_bnd.resize(nblk + 1);
-    M.blk_bnd_rec.resize(nblk);
-    for (int64_t b = 0; b <= nblk; ++b) M.blk_bnd[b] = int32_t(blk_bnd[b]);
-    for (int64_t b = 0; b < nblk; ++b)
-        M.blk_bnd_rec[b] = M.blk_edge[b] + n_cross[b];
+    M.blk_bnd.assign(4 * size_t(nblk), 0);
+    for (int64_t b = 0; b < nblk; ++b) {
+        M.blk_bnd[4 * b] = int32_t(blk_bnd[b]);
+        M.blk_bnd[4 * b + 1] = M.blk_edge[b] + n_cross[b];
+        M.blk_bnd[4 * b + 2] = int32_t(blk_bnd[b + 1] - blk_bnd[b]);
+    }
     M.max_block_edges = emax;
     const int64_t nbe = M.blk_edge[nblk];
     M.be_a.resize(nbe);

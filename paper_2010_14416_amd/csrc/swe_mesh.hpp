@@ -42,10 +42,11 @@ struct BlockMesh {
     std::vector<double> be_nx, be_ny, be_len;
 
     // tag of each boundary slot; slots are numbered in block order. Block b
-    // holds slots [blk_bnd[b], blk_bnd[b+1]), whose records are consecutive
-    // from record blk_bnd_rec[b] on (after the edges to other blocks).
+    // holds the blk_bnd[4b+2] slots from blk_bnd[4b] on, whose records are
+    // consecutive from record blk_bnd[4b+1] on (after the edges to other
+    // blocks); blk_bnd[4b+3] = 0 pads the entry to 16 bytes.
     std::vector<int32_t> bnd_tag;
-    std::vector<int32_t> blk_bnd, blk_bnd_rec;
+    std::vector<int32_t> blk_bnd;
 
     // total boundary length per tag (inflow discharge per unit length)
     std::vector<double> tag_length;

@@ -287,6 +287,32 @@ def test_monitors_match_the_oracle_and_leave_the_state_alone():
     assert np.all(hm >= s.state()[0])
 
 
+def test_envelope_is_the_running_maximum_of_the_states():
+    """Bitwise: the envelope equals the maximum over the run's own states
+    (rising, falling and re-rising cells; reading it mid-run changes
+    nothing) and t_wet is the end time of the first step with h > h_dry."""
+    case = W.bumps_canal(nx=90, ny=31, lx=30.0, ly=10.0, x_dam=15.0)
+    say(f"[envelope] {case.name} cells={case.n_cells}")
+    s = solver(case, params={"monitors": 1})
+    h = s.state()[0]
+    hmax = h.copy()
+    twet = np.where(h > case.h_dry, 0.0, np.inf)
+    falls = 0
+    for k in range(120):
+        s.advance(1)
+        hn = s.state()[0]
+        t = s.time()[0]
+        falls += int(np.sum((hn < h) & (h == hmax)))
+        twet = np.where(np.isinf(twet) & (hn > case.h_dry), t, twet)
+        hmax = np.maximum(hmax, hn)
+        h = hn
+        if k % 17 == 3 or k == 119:
+            hm, tw = s.envelope()
+            assert np.array_equal(hm, hmax), k
+            assert np.array_equal(tw, twet), k
+    assert falls > 0 and np.any(hmax > h)
+
+
 def test_monitors_closed_canal_reset_and_off():
     from paper_2010_14416_amd import swe as S
     case = W.dam_break_canal()
