@@ -213,6 +213,9 @@ def main():
                     help="ensemble members (--workload ensemble)")
     ap.add_argument("--solo-sample", type=int, default=16,
                     help="ensemble members also timed one at a time")
+    ap.add_argument("--no-group-wet", action="store_true",
+                    help="order cells along the curve only, without first "
+                         "grouping the initially wet cells apart")
     ap.add_argument("--fd-directions", type=int, default=32,
                     help="finite-difference checks of the adjoint")
 
@@ -253,6 +256,7 @@ def main():
         bc, bt = int(m.group(1)), int(m.group(2))
         sched, mon, sall = (int(m.group(k) or 0) for k in (3, 4, 5))
         sw = Solver(case, device=0, block_cells=bc,
+                    group_wet=not args.no_group_wet,
                     params={"block_threads": bt, "load_schedule": sched,
                             "monitors": mon, "store_all": sall})
         sw.advance(args.warmup + 1, want_time=True)
@@ -275,6 +279,7 @@ def main():
 
     t0 = time.perf_counter()
     s = Solver(case, device=0, block_cells=args.block_cells,
+               group_wet=not args.no_group_wet,
                params={"block_threads": args.block_threads})
     info = s.info()
     s.advance(1, want_time=True)          # device set-up + first step
@@ -350,6 +355,7 @@ def run_ensemble(args):
         f"({time.perf_counter() - t0:.1f} s to generate)")
     t1 = time.perf_counter()
     ens = Ensemble(cases, block_cells=args.block_cells,
+                   group_wet=not args.no_group_wet,
                    params={"block_threads": args.block_threads})
     ens.advance(args.warmup)
     ens.time(0)
@@ -374,6 +380,7 @@ def run_ensemble(args):
     solo_ms, solo_cells = [], 0
     for k in pick:
         s = Solver(cases[k], device=0, block_cells=args.block_cells,
+                   group_wet=not args.no_group_wet,
                    params={"block_threads": args.block_threads})
         s.advance(args.warmup, want_time=True)
         torch.cuda.synchronize()

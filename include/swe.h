@@ -154,6 +154,16 @@ swe_status swe_set_mesh(swe_ctx *ctx, int64_t n_nodes, const double *xy,
                         int64_t n_cells, const int32_t *tri, int64_t n_bnd,
                         const int32_t *bnd_nodes, const int32_t *bnd_tag);
 
+/* Cell groups for the next swe_set_mesh (with reorder = 1): cells are
+ * ordered by group value first and along the space-filling curve within a
+ * group. n_cells values in user order (copied; n_cells = 0 clears them); the
+ * next swe_set_mesh uses and clears them, and fails with SWE_EINVAL if its
+ * cell count differs. Grouping the cells that hold water at the start apart
+ * from the dry ones makes blocks wet or dry as a whole, and a dry block
+ * costs next to nothing; results do not depend on the order. */
+swe_status swe_set_cell_groups(swe_ctx *ctx, int64_t n_cells,
+                               const uint8_t *group);
+
 /* Counts and sizes of the current mesh. */
 swe_status swe_mesh_info(const swe_ctx *ctx, swe_mesh_stats *out);
 

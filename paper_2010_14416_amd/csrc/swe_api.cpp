@@ -432,6 +432,16 @@ swe_status swe_get_params(const swe_ctx *c, swe_params *p)
     return SWE_OK;
 }
 
+swe_status swe_set_cell_groups(swe_ctx *c, int64_t n_cells,
+                               const uint8_t *group)
+{
+    if (!c) return SWE_EINVAL;
+    if (n_cells < 0 || (n_cells > 0 && !group))
+        return fail(c, SWE_EINVAL, "null or negative cell groups");
+    c->groups.assign(group, group + n_cells);
+    return SWE_OK;
+}
+
 swe_status swe_set_mesh(swe_ctx *c, int64_t n_nodes, const double *xy,
                         int64_t n_cells, const int32_t *tri, int64_t n_bnd,
                         const int32_t *bnd_nodes, const int32_t *bnd_tag)
@@ -439,12 +449,19 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t n_nodes, const double *xy,
     if (!c) return SWE_EINVAL;
     if (!xy || !tri || n_bnd < 0 || (n_bnd > 0 && (!bnd_nodes || !bnd_tag)))
         return fail(c, SWE_EINVAL, "null mesh array");
+    if (!c->groups.empty() && int64_t(c->groups.size()) != n_cells) {
+        c->groups.clear();
+        return fail(c, SWE_EINVAL,
+                    "cell groups were set for a different number of cells");
+    }
     BlockMesh m;
     std::string err;
-    if (!swe::build_block_mesh(n_nodes, xy, n_cells, tri, n_bnd, bnd_nodes,
-                               bnd_tag, c->params.block_cells,
-                               c->params.reorder != 0, SWE_MAX_TAG, m, err))
-        return fail(c, SWE_EMESH, err);
+    const bool ok = swe::build_block_mesh(
+        n_nodes, xy, n_cells, tri, n_bnd, bnd_nodes, bnd_tag,
+        c->params.block_cells, c->params.reorder != 0,
+        c->groups.empty() ? nullptr : c->groups.data(), SWE_MAX_TAG, m, err);
+    c->groups.clear();
+    if (!ok) return fail(c, SWE_EMESH, err);
     if (c->ws_owned && c->ws) {
         (void)hipSetDevice(c->device);
         (void)hipFree(c->ws);

@@ -44,6 +44,7 @@ struct swe_ctx {
     std::string err;
     bool has_mesh = false;
     swe::BlockMesh mesh;
+    std::vector<uint8_t> groups;   // cell groups for the next set_mesh
     // host copies in internal order; *_dirty: newer than the device copy
     std::vector<double> z, man, h, hu, hv;
     bool z_dirty = false, man_dirty = false, state_dirty = false;

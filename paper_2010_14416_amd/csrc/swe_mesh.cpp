@@ -72,8 +72,9 @@ void radix_sort_u64(std::vector<uint64_t> &a, int lo_bit)
 bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
                       const int32_t *tri_in, int64_t nbnd,
                       const int32_t *bnd_nodes, const int32_t *bnd_tag,
-                      int32_t block_cells, bool reorder, int32_t max_tag,
-                      BlockMesh &M, std::string &err)
+                      int32_t block_cells, bool reorder,
+                      const uint8_t *group, int32_t max_tag, BlockMesh &M,
+                      std::string &err)
 {
     M = BlockMesh();
     if (nn < 3 || nc < 1) {
@@ -375,6 +376,18 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < nc; ++i)
             order[i] = int32_t(key[i] & 0xffffffffu);
+        // groups in ascending order, each along the curve: with the cells
+        // holding water in one group, blocks are wet or dry as a whole
+        // except at the seams, and dry blocks cost next to nothing
+        if (group) {
+            std::vector<int64_t> start(257, 0);
+            for (int64_t c = 0; c < nc; ++c) ++start[size_t(group[c]) + 1];
+            for (int k = 0; k < 256; ++k) start[k + 1] += start[k];
+            std::vector<int32_t> by_group(nc);
+            for (int64_t i = 0; i < nc; ++i)
+                by_group[start[group[order[i]]]++] = order[i];
+            order.swap(by_group);
+        }
     } else {
         std::iota(order.begin(), order.end(), 0);
     }

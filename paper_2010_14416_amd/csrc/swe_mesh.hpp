@@ -53,10 +53,14 @@ struct BlockMesh {
 };
 
 // Builds the block mesh. Returns false and sets err on an invalid mesh.
+// With reorder, cells follow a Hilbert curve through their centroids; with
+// group (one value per cell, or null) too, cells are ordered by group first
+// and along the curve within a group.
 bool build_block_mesh(int64_t n_nodes, const double *xy, int64_t n_cells,
                       const int32_t *tri, int64_t n_bnd,
                       const int32_t *bnd_nodes, const int32_t *bnd_tag,
-                      int32_t block_cells, bool reorder, int32_t max_tag,
-                      BlockMesh &out, std::string &err);
+                      int32_t block_cells, bool reorder,
+                      const uint8_t *group, int32_t max_tag, BlockMesh &out,
+                      std::string &err);
 
 }  // namespace swe

@@ -108,6 +108,8 @@ def load():
     L.swe_set_mesh.restype = st
     L.swe_set_mesh.argtypes = [_p, C.c_int64, _pd, C.c_int64, _pi32,
                                C.c_int64, _pi32, _pi32]
+    L.swe_set_cell_groups.restype = st
+    L.swe_set_cell_groups.argtypes = [_p, C.c_int64, C.POINTER(C.c_uint8)]
     L.swe_mesh_info.restype = st
     L.swe_mesh_info.argtypes = [_p, C.POINTER(swe_mesh_stats)]
     L.swe_get_cell_order.restype = st
@@ -264,6 +266,17 @@ def swe_set_mesh(ctx, xy, tri, bnd=None, bnd_tag=None):
         ctx, xy.shape[0], xy.ctypes.data_as(_pd), tri.shape[0],
         tri.ctypes.data_as(_pi32), bnd.shape[0], bnd.ctypes.data_as(_pi32),
         bnd_tag.ctypes.data_as(_pi32)))
+
+
+def swe_set_cell_groups(ctx, group):
+    """Cell groups (uint8, user order) for the next swe_set_mesh; None
+    clears them."""
+    if group is None:
+        _check(ctx, load().swe_set_cell_groups(ctx, 0, None))
+        return
+    g = np.ascontiguousarray(group, dtype=np.uint8).reshape(-1)
+    _check(ctx, load().swe_set_cell_groups(
+        ctx, g.size, g.ctypes.data_as(C.POINTER(C.c_uint8))))
 
 
 def swe_mesh_info(ctx):
@@ -504,10 +517,12 @@ def swe_ens_info(ens):
 class Solver:
     """One context set up from a workloads.Case. With workspace="torch" the
     device memory is a torch uint8 tensor bound through swe_bind_workspace;
-    with stream="torch" kernels run on torch's current stream."""
+    with stream="torch" kernels run on torch's current stream. With
+    group_wet (and reorder), the cells holding water in the case's state
+    are ordered apart from the dry ones (swe_set_cell_groups)."""
 
     def __init__(self, case, device=0, workspace="torch", stream="torch",
-                 block_cells=256, reorder=True, params=None):
+                 block_cells=256, reorder=True, params=None, group_wet=True):
         self.ctx = swe_create(device)
         self._ws = None
         self.device = device
@@ -520,6 +535,8 @@ class Solver:
                 for k, v in params.items():
                     setattr(p, k, v)
             swe_set_params(self.ctx, p)
+            if group_wet and reorder:
+                swe_set_cell_groups(self.ctx, np.where(case.h > p.h_dry, 0, 1))
             swe_set_mesh(self.ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
             for tag, (kind, value) in case.bc.items():
                 swe_set_bc(self.ctx, tag, kind, value)
@@ -592,9 +609,10 @@ class Ensemble:
     workspace / stream are None."""
 
     def __init__(self, cases, device=0, block_cells=256, params=None,
-                 workspace="torch", stream="torch"):
+                 workspace="torch", stream="torch", group_wet=True):
         self.members = [Solver(c, device=device, workspace=None, stream=None,
-                               block_cells=block_cells, params=params)
+                               block_cells=block_cells, params=params,
+                               group_wet=group_wet)
                         for c in cases]
         self.n_cells = [c.n_cells for c in cases]
         self.ens = swe_ens_create([m.ctx for m in self.members])

@@ -76,6 +76,46 @@ def test_cell_order_is_a_permutation_that_restores_locality(ctx):
     assert info["n_block_edges"] < 1.25 * info["n_edges"]
 
 
+def test_cell_groups_order_cells_by_group_then_along_the_curve(ctx):
+    case = W.river(n_target=40_000, workers=1)
+    wet = case.h > case.h_dry
+    S.swe_set_mesh(ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
+    curve = S.swe_get_cell_order(ctx)
+    S.swe_set_cell_groups(ctx, np.where(wet, 0, 1))
+    S.swe_set_mesh(ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
+    grouped = S.swe_get_cell_order(ctx)
+    n_wet = int(wet.sum())
+    assert 0 < n_wet < case.n_cells
+    # wet cells first, each group in the curve order of the plain reorder
+    assert np.array_equal(np.sort(grouped[wet]), np.arange(n_wet))
+    for g in (wet, ~wet):
+        users = np.flatnonzero(g)
+        assert np.array_equal(users[np.argsort(grouped[users])],
+                              users[np.argsort(curve[users])])
+    # blocks of 256 cells: only the seam block mixes wet and dry cells
+    blocks = (np.arange(case.n_cells) // 256)
+    inv = np.empty(case.n_cells, np.int64)
+    inv[grouped] = np.arange(case.n_cells)
+    wet_int = wet[inv]
+    mixed = [b for b in range(blocks[-1] + 1)
+             if 0 < wet_int[b * 256:(b + 1) * 256].sum() <
+             len(wet_int[b * 256:(b + 1) * 256])]
+    assert len(mixed) <= 1
+    # the groups were used and cleared: the next mesh is curve-ordered
+    S.swe_set_mesh(ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
+    assert np.array_equal(S.swe_get_cell_order(ctx), curve)
+
+
+def test_cell_groups_of_another_size_are_rejected(ctx):
+    case = W.bumps_canal(nx=20, ny=10)
+    S.swe_set_cell_groups(ctx, np.zeros(case.n_cells + 1, np.uint8))
+    with pytest.raises(S.SweError) as e:
+        S.swe_set_mesh(ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
+    assert e.value.status == S.SWE_EINVAL
+    # cleared by the failed call
+    S.swe_set_mesh(ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
+
+
 def test_reorder_off_keeps_user_order(ctx):
     case = W.bumps_canal(nx=20, ny=10)
     p = S.swe_default_params()

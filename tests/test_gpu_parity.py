@@ -118,6 +118,36 @@ def test_blocking_and_order_do_not_change_bits(block_cells, reorder,
         assert np.array_equal(x, y)
 
 
+def test_wet_grouped_order_gives_identical_bits():
+    """Cells grouped by their initial wet state (the default) or along the
+    curve only: same states, same time, monitors alike."""
+    case = W.river(n_target=60_000, workers=1)
+    a = solver(case, group_wet=True, params={"monitors": 1})
+    b = solver(case, group_wet=False, params={"monitors": 1})
+    assert not np.array_equal(S_order(a), S_order(b))
+    a.advance(80)
+    b.advance(80)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    assert a.time() == b.time()
+    for x, y in zip(a.envelope(), b.envelope()):
+        assert np.array_equal(x, y)
+    for tag in (0, 1, 2):
+        # per-slot values are the same bits; a tag sums its slots in block
+        # order, which differs
+        for x, y in zip(a.discharge(tag), b.discharge(tag)):
+            assert abs(x - y) <= 1e-12 * max(abs(x), 1.0)
+    ma, la, wa = a.diagnostics()
+    mb, lb, wb = b.diagnostics()
+    assert wa == wb and abs(ma - mb) <= 1e-12 * ma
+    assert abs(la - lb) <= 1e-12 * max(abs(la), 1e-300) + 1e-300
+
+
+def S_order(s):
+    from paper_2010_14416_amd import swe as S
+    return S.swe_get_cell_order(s.ctx)
+
+
 def test_user_cell_permutation_gives_identical_bits():
     case = W.bumps_canal(nx=90, ny=31, lx=30.0, ly=10.0, x_dam=15.0)
     perm = np.random.default_rng(1).permutation(case.n_cells)
