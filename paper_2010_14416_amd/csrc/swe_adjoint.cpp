@@ -260,6 +260,7 @@ extern "C" swe_status swe_adjoint_gauges(swe_ctx *c, int64_t steps,
     if ((st = copy_state(c, final_state, true))) return st;
     ADJCHK(c, swe::launch_fill_u32((unsigned *)c->d.quiet, 0u, int64_t(nb),
                                    c->stream));
+    ADJCHK(c, swe::launch_fill_u32(c->d.run, 1u, 2 * int64_t(nb), c->stream));
     ADJCHK(c, hipMemcpyAsync(c->d.ledger, ledger_copy, nb * 8,
                              hipMemcpyDeviceToDevice, c->stream));
     ADJCHK(c, swe::launch_clock_set(c->d.clock, t_final, steps_final,

@@ -84,6 +84,8 @@ size_t layout(const BlockMesh &m, char *base, DevBufs *d)
     t.mon_rate = (double *)take(nbnd * 8);
     t.mon_vol = (double *)take(nbnd * 8);
     t.blk_bnd = (int32_t *)take(nb * 16);
+    t.blk_nbr = (int32_t *)take(m.blk_nbr.size() * 4);
+    t.run = (uint32_t *)take(2 * nb * 4);
     t.h_max = (double *)take(nc * 8);
     t.t_wet = (double *)take(nc * 8);
     t.part_mass = (double *)take(kDiagParts * 8);
@@ -152,6 +154,8 @@ swe_status prepare(swe_ctx *c)
             return st;
         if ((st = upload(c, d.blk_bnd, m.blk_bnd.data(), m.blk_bnd.size())))
             return st;
+        if ((st = upload(c, d.blk_nbr, m.blk_nbr.data(), m.blk_nbr.size())))
+            return st;
         const size_t nbe = m.be_a.size();
         if ((st = upload(c, d.be_a, m.be_a.data(), nbe))) return st;
         if ((st = upload(c, d.be_b, m.be_b.data(), nbe))) return st;
@@ -167,6 +171,9 @@ swe_status prepare(swe_ctx *c)
         c->cur_slot = 0;
     }
     DevBufs &d = c->d;
+    // any input of the step changed: no block may be taken as dormant
+    if (c->z_dirty || c->man_dirty || c->gm2_dirty || c->bc_dirty)
+        c->quiet_dirty = true;
     if (c->z_dirty) {
         if ((st = upload(c, d.z, c->z.data(), nc))) return st;
         c->z_dirty = false;
@@ -190,8 +197,11 @@ swe_status prepare(swe_ctx *c)
         c->mon_dirty = true;
     }
     if (c->quiet_dirty) {
-        // the step kernel may skip stores only after two steps from here
+        // the step kernel may skip stores, and dormant blocks, only after
+        // two steps from here
         HIPCHK(c, swe::launch_fill_u32((unsigned *)d.quiet, 0u, m.n_blocks,
+                                       c->stream));
+        HIPCHK(c, swe::launch_fill_u32(d.run, 1u, 2 * int64_t(m.n_blocks),
                                        c->stream));
         c->quiet_dirty = false;
     }
@@ -421,7 +431,10 @@ swe_status swe_set_params(swe_ctx *c, const swe_params *p)
     if (p->monitors && !c->params.monitors) c->mon_dirty = true;
     c->params = *p;
     if (g_changed) c->gm2_dirty = true;
-    if (dt_changed) c->dt_valid = false;
+    if (dt_changed) {
+        c->dt_valid = false;
+        c->quiet_dirty = true;
+    }
     return SWE_OK;
 }
 
@@ -696,6 +709,9 @@ StepArgs ctx_step_args(swe_ctx *c, double t_end)
     a.clock = c->d.clock;
     a.ledger = c->d.ledger;
     a.quiet = c->d.quiet;
+    a.blk_nbr = c->d.blk_nbr;
+    a.run = c->d.run;
+    a.skip_dormant = m.nbr_complete ? 1 : 0;
     a.store_all = c->params.store_all;
     if (c->params.monitors) {
         a.mon_rate = c->d.mon_rate;

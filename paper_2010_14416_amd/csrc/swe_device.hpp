@@ -61,6 +61,10 @@ struct StepArgs {
     double *ledger;           // per block: mass added by the positivity fix
     int32_t *quiet;           // per block: consecutive steps (capped at 2) in
                               // which every cell took the quiet dry path
+    // dormant blocks: per block kNbrSlots neighbour blocks (-1 padded), and
+    // run marks for even and odd step indices (2 x n_blocks); a block runs
+    // at step k if it or a neighbour was not quiet for two steps at step
+    // k - 1, or if skip_dormant is 0
     // monitors (all null when off): per boundary slot the outward volume
     // rate of the last step and the volume since the last reset; per cell
     // the highest depth and the first time with h > h_dry (+inf: never)
@@ -74,6 +78,9 @@ struct StepArgs {
     // sign bit set on the member's first block; per member the end of its
     // cell range and its end time; `clock` then points to one clock per
     // member
+    const int32_t *blk_nbr;
+    uint32_t *run;
+    int32_t skip_dormant;
     const int32_t *blk_member;
     const int32_t *member_end;
     const double *t_end_m;

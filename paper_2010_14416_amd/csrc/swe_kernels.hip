@@ -74,9 +74,10 @@ __device__ __forceinline__ double wave_sum(double v)
 // End of a step for one block: wave-shuffle then LDS reductions of the
 // block's min R_i/s_i (one 64-bit atomic min into the next clock slot), of
 // the mass added by the positivity fix, and of the non-finite flag; block 0
-// advances the clock.
+// advances the clock. Returns the block's new count of consecutive quiet
+// steps (capped at 2) to every thread.
 template <int NT>
-__device__ __forceinline__ void block_finish(const StepArgs &a, int blk,
+__device__ __forceinline__ int block_finish(const StepArgs &a, int blk,
                                              Clock *clock, bool first,
                                              double rs, double clamp,
                                              unsigned bad, bool active,
@@ -97,6 +98,9 @@ __device__ __forceinline__ void block_finish(const StepArgs &a, int blk,
         red_bad[wave] = (ballot != 0ull ? 1u : 0u) | (busy != 0ull ? 2u : 0u);
     }
     __syncthreads();
+    unsigned busy_any = 0u;
+    for (int w = 0; w < NT / 64; ++w) busy_any |= red_bad[w] & 2u;
+    const int q = busy_any ? 0 : min(quiet_steps + 1, 2);
     if (tid == 0) {
         double m = red_min[0], cs = red_sum[0];
         unsigned flags = red_bad[0];
@@ -106,7 +110,6 @@ __device__ __forceinline__ void block_finish(const StepArgs &a, int blk,
             flags |= red_bad[w];
         }
         const bool anybad = (flags & 1u) != 0u;
-        const int q = (flags & 2u) ? 0 : min(quiet_steps + 1, 2);
         if (q != quiet_steps) a.quiet[blk] = q;
         if (m < INFINITY)
             atomicMin(&clock->minrs[nxt][blockIdx.x & (kClockLanes - 1)][0],
@@ -126,6 +129,7 @@ __device__ __forceinline__ void block_finish(const StepArgs &a, int blk,
                 atomicExch(&clock->minrs[nn][x][0], kInfBits);
         }
     }
+    return q;
 }
 
 // Clock words of this step, read with one vector load per lane so that they
@@ -211,6 +215,7 @@ void swe_step_kernel(StepArgs a)
     __shared__ double red_sum[NT / 64];
     __shared__ unsigned red_bad[NT / 64];
     __shared__ int4 s_bnd[1];
+    __shared__ int32_t s_nbr[kNbrSlots];
     double *s_h = lds;
     double *s_u = s_h + NC;
     double *s_v = s_u + NC;
@@ -220,6 +225,12 @@ void swe_step_kernel(StepArgs a)
     const int tid = threadIdx.x;
     const int blk = a.blk_base + xcd_block(blockIdx.x, a.n_blocks);
     const int c0 = blk * NC;
+    // dormant blocks: a block that, like each of its neighbour blocks, took
+    // the quiet dry path in the two previous steps has the inputs it had
+    // one step ago, so it would compute (and hold) the same quiet results.
+    // Such a block was not marked to run by any block of the previous step
+    // and returns at once (the clock's block always runs).
+    const size_t run_at = size_t(a.step_index & 1) * size_t(a.n_blocks);
     // one mesh, or member `mem` of an ensemble (its cells start on a block)
     int mem = 0, cell_end = a.n_cells;
     bool first = blk == 0;
@@ -243,6 +254,7 @@ void swe_step_kernel(StepArgs a)
 
     // phase 1: owned cell, first edge record (+ geometry), neighbour state
     const int quiet_steps = a.quiet[blk];
+    const uint32_t run_me = a.run[run_at + blk];
     // the block's boundary slots (discharge monitors), to LDS with phase 1
     int4 bnd = make_int4(0, 0, 0, 0);
     if (MON && tid == NC / 64)
@@ -268,6 +280,9 @@ void swe_step_kernel(StepArgs a)
         ea2 = a.be_a[e0 + tid + NT];
         eb2 = a.be_b[e0 + tid + NT];
     }
+    if (a.skip_dormant && !a.store_all && !first && run_me == 0u) return;
+    int32_t nbr = -1;   // neighbour blocks, to LDS with phase 1
+    if (tid < kNbrSlots) nbr = a.blk_nbr[blk * kNbrSlots + tid];
     // the momentum of a dry cell is read in phase 3, and only if needed
     if (owner && h > h_dry) {
         hu = a.hu0[i];
@@ -298,6 +313,7 @@ void swe_step_kernel(StepArgs a)
     }
     const StepTime st = step_time(a, cw, t_end);
     if (MON && tid == NC / 64) s_bnd[0] = bnd;
+    if (tid < kNbrSlots) s_nbr[tid] = nbr;
     if (owner) {
         s_h[tid] = h;
         s_z[tid] = zc;
@@ -444,9 +460,21 @@ void swe_step_kernel(StepArgs a)
             rs = inr / (sqrt(g * hn) + sqrt(u * u + v * v));
         }
     }
-    block_finish<NT>(a, blk, clock, first, rs, clamp, bad, active,
-                     quiet_steps, st.unbounded, st.dt, st.tn,
-                     a.cur == 2 ? 0 : a.cur + 1, red_min, red_sum, red_bad);
+    const int q = block_finish<NT>(a, blk, clock, first, rs, clamp, bad,
+                                   active, quiet_steps, st.unbounded, st.dt,
+                                   st.tn, a.cur == 2 ? 0 : a.cur + 1, red_min,
+                                   red_sum, red_bad);
+    {
+        // this step's mark is used up; a block not quiet for two steps
+        // marks itself and its neighbour blocks to run at the next step
+        const size_t next = size_t(a.n_blocks) - run_at;
+        if (tid == 0 && run_me) a.run[run_at + blk] = 0u;
+        if (q < 2) {
+            if (tid == 0) a.run[next + blk] = 1u;
+            if (tid < kNbrSlots && s_nbr[tid] >= 0)
+                a.run[next + s_nbr[tid]] = 1u;
+        }
+    }
     // the stores come last: no instruction after them waits for a load, so
     // the wave never waits for its own stores. A quiet cell of a block quiet
     // in the two previous steps already holds (h, 0, 0) in the output buffer

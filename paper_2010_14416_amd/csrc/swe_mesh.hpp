@@ -48,9 +48,18 @@ struct BlockMesh {
     std::vector<int32_t> bnd_tag;
     std::vector<int32_t> blk_bnd;
 
+    // per block kNbrSlots entries: the other blocks it shares an edge with,
+    // then -1; nbr_complete is false if some block has more (dormant blocks
+    // are then never skipped)
+    std::vector<int32_t> blk_nbr;
+    bool nbr_complete = true;
+
     // total boundary length per tag (inflow discharge per unit length)
     std::vector<double> tag_length;
 };
+
+// Neighbour blocks kept per block for skipping dormant blocks.
+constexpr int kNbrSlots = 32;
 
 // Builds the block mesh. Returns false and sets err on an invalid mesh.
 // With reorder, cells follow a Hilbert curve through their centroids; with

@@ -118,6 +118,50 @@ def test_blocking_and_order_do_not_change_bits(block_cells, reorder,
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("name", ["bumps", "river"])
+def test_dormant_blocks_and_skipped_stores_change_no_bit(name):
+    """Blocks that stay quiet with quiet neighbours are skipped, and quiet
+    blocks skip their stores; store_all = 1 turns both off. Same bits over
+    runs whose wet/dry fronts cross dry blocks, through a state reset, a
+    bathymetry change and a frozen time-step schedule."""
+    from paper_2010_14416_amd import swe as S
+    case = (W.bumps_canal(nx=120, ny=40, lx=30.0, ly=10.0, x_dam=8.0)
+            if name == "bumps" else W.river(n_target=120_000, workers=1))
+    say(f"[dormant] {case.name} cells={case.n_cells}")
+    a = solver(case, params={"monitors": 1})
+    b = solver(case, params={"monitors": 1, "store_all": 1})
+
+    def same():
+        for x, y in zip(a.state(), b.state()):
+            assert np.array_equal(x, y)
+        assert a.time() == b.time()
+        for x, y in zip(a.envelope(), b.envelope()):
+            assert np.array_equal(x, y)
+
+    for s in (a, b):
+        s.advance(150)
+    same()
+    # a state reset halfway through a run
+    h, hu, hv = a.state()
+    h2 = h.copy()
+    h2[: h.size // 7] += 0.05
+    for s in (a, b):
+        s.set_state(h2, hu, hv)
+        s.advance(60)
+    same()
+    # a changed bed
+    z2 = case.z.copy()
+    z2[h2 <= case.h_dry] -= 0.01
+    for s in (a, b):
+        S.swe_set_bathymetry(s.ctx, z2)
+        s.advance(60)
+    same()
+    # frozen time steps
+    dts = S.swe_advance_dt(a.ctx, 40, None, record=True)
+    S.swe_advance_dt(b.ctx, 40, dts)
+    same()
+
+
 def test_wet_grouped_order_gives_identical_bits():
     """Cells grouped by their initial wet state (the default) or along the
     curve only: same states, same time, monitors alike."""
