@@ -62,6 +62,22 @@ def test_members_match_their_own_runs_bitwise():
         assert (et, edt, estep) == (t, dt, step)
 
 
+def test_dormant_blocks_change_no_member_bit():
+    """The ensemble with dormant-block skipping and store skipping (the
+    default) against the ensemble with both off (store_all = 1), over a run
+    long enough for dry blocks to fall dormant and fronts to wake them."""
+    from paper_2010_14416_amd import Ensemble
+    cases = members()
+    a = Ensemble(cases)
+    b = Ensemble(cases, params={"store_all": 1})
+    a.advance(200)
+    b.advance(200)
+    for k in range(len(cases)):
+        for x, y in zip(a.state(k), b.state(k)):
+            assert np.array_equal(x, y)
+        assert a.time(k) == b.time(k)
+
+
 def test_members_stop_at_their_own_end_times():
     from paper_2010_14416_amd import Ensemble
     cases = members()[:4]
