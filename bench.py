@@ -213,6 +213,9 @@ def main():
                     help="ensemble members (--workload ensemble)")
     ap.add_argument("--solo-sample", type=int, default=16,
                     help="ensemble members also timed one at a time")
+    ap.add_argument("--no-every-block", action="store_true",
+                    help="skip the second timing with every block computed "
+                         "and stored (store_all = 1)")
     ap.add_argument("--no-group-wet", action="store_true",
                     help="order cells along the curve only, without first "
                          "grouping the initially wet cells apart")
@@ -299,6 +302,24 @@ def main():
     t_sim, last_dt, step = s.time()       # also raises on a numeric fault
     log(f"{args.steps} steps in {elapsed_ms:.2f} ms; t = {t_sim:.4f} s, "
         f"dt = {last_dt:.4g} s")
+    # the same steps with every block computed and stored (store_all = 1:
+    # no dormant blocks skipped, no quiet stores skipped); same results
+    every_ms = None
+    if not args.no_every_block:
+        s.close()
+        s = Solver(case, device=0, block_cells=args.block_cells,
+                   group_wet=not args.no_group_wet,
+                   params={"block_threads": args.block_threads,
+                           "store_all": 1})
+        s.advance(args.warmup + 1, want_time=True)
+        torch.cuda.synchronize()
+        ev0.record(s.stream)
+        s.advance(args.steps)
+        ev1.record(s.stream)
+        torch.cuda.synchronize()
+        every_ms = ev0.elapsed_time(ev1) / args.steps
+        s.time()
+        log(f"every block computed: {every_ms:.4f} ms per step")
 
     copy_gbs = None
     if args.copy_mb > 0:
@@ -332,7 +353,8 @@ def main():
                     block_cells=info["block_cells"],
                     block_threads=args.block_threads or info["block_cells"],
                     setup_s=round(setup_s, 2),
-                    effective_gbs=achieved),
+                    effective_gbs=achieved,
+                    every_block_ms_per_step=every_ms),
         roofline=roofline, cpu_baseline=base)
     print(json.dumps(out), flush=True)
     s.close()
