@@ -162,6 +162,20 @@ def test_dormant_blocks_and_skipped_stores_change_no_bit(name):
     same()
 
 
+def test_user_order_without_dormant_blocks_gives_identical_bits():
+    """A shuffled mesh kept in user order (reorder = 0): its blocks
+    neighbour more blocks than the table holds, so none is ever skipped;
+    same bits as the default order, which skips dormant blocks."""
+    case = W.river(n_target=30_000, workers=1)        # cells shuffled
+    a = solver(case)
+    b = solver(case, reorder=False)
+    for s in (a, b):
+        s.advance(120)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    assert a.time() == b.time()
+
+
 def test_wet_grouped_order_gives_identical_bits():
     """Cells grouped by their initial wet state (the default) or along the
     curve only: same states, same time, monitors alike."""
