@@ -88,6 +88,7 @@ size_t layout(const BlockMesh &m, char *base, DevBufs *d)
     t.run = (uint32_t *)take(2 * nb * 4);
     t.h_max = (double *)take(nc * 8);
     t.t_wet = (double *)take(nc * 8);
+    t.mon = (swe::MonPtrs *)take(sizeof(swe::MonPtrs));
     t.part_mass = (double *)take(kDiagParts * 8);
     t.part_wet = (unsigned long long *)take(kDiagParts * 8);
     t.flag = (unsigned *)take(256);
@@ -156,6 +157,9 @@ swe_status prepare(swe_ctx *c)
             return st;
         if ((st = upload(c, d.blk_nbr, m.blk_nbr.data(), m.blk_nbr.size())))
             return st;
+        c->mon_host = swe::MonPtrs{d.mon_rate, d.mon_vol, d.blk_bnd, d.h_max,
+                              d.t_wet};
+        if ((st = upload(c, d.mon, &c->mon_host, 1))) return st;
         const size_t nbe = m.be_a.size();
         if ((st = upload(c, d.be_a, m.be_a.data(), nbe))) return st;
         if ((st = upload(c, d.be_b, m.be_b.data(), nbe))) return st;
@@ -713,13 +717,7 @@ StepArgs ctx_step_args(swe_ctx *c, double t_end)
     a.run = c->d.run;
     a.skip_dormant = m.nbr_complete ? 1 : 0;
     a.store_all = c->params.store_all;
-    if (c->params.monitors) {
-        a.mon_rate = c->d.mon_rate;
-        a.mon_vol = c->d.mon_vol;
-        a.blk_bnd = c->d.blk_bnd;
-        a.h_max = c->d.h_max;
-        a.t_wet = c->d.t_wet;
-    }
+    if (c->params.monitors) a.mon = c->d.mon;
     a.g = c->params.g;
     a.cfl = c->params.cfl;
     a.h_dry = c->params.h_dry;
@@ -744,11 +742,7 @@ swe_status ctx_step_between(swe_ctx *c, const double *const in[3],
     a.cfl = INFINITY;   // dt = min(cfl * min R/s, dt_max) = dt exactly
     a.dt_max = dt;
     a.store_all = 1;    // `out` need not hold the state before `in`
-    a.mon_rate = nullptr;
-    a.mon_vol = nullptr;
-    a.blk_bnd = nullptr;
-    a.h_max = nullptr;
-    a.t_wet = nullptr;
+    a.mon = nullptr;
     a.cur = c->cur_slot;
     a.step_index = c->step_index;
     const int threads = c->params.block_threads == 0

@@ -30,6 +30,7 @@ struct DevBufs {
     int32_t *blk_nbr;             // per block, kNbrSlots neighbour blocks
     uint32_t *run;                // run marks, 2 x n_blocks
     double *h_max, *t_wet;        // per cell (internal order)
+    MonPtrs *mon;                 // the five monitor addresses above
     double *part_mass;
     unsigned long long *part_wet;
     unsigned *flag;
@@ -47,6 +48,7 @@ struct swe_ctx {
     bool has_mesh = false;
     swe::BlockMesh mesh;
     std::vector<uint8_t> groups;   // cell groups for the next set_mesh
+    swe::MonPtrs mon_host{};       // source of the device copy d.mon
     // host copies in internal order; *_dirty: newer than the device copy
     std::vector<double> z, man, h, hu, hv;
     bool z_dirty = false, man_dirty = false, state_dirty = false;

@@ -37,6 +37,18 @@ struct Clock {
     unsigned long long minrs[3][kClockLanes][16];
 };
 
+// Monitors: per boundary slot the outward volume rate of the last step and
+// the volume since the last reset; per block 4 values {first slot, record
+// of the first slot, slots, 0}; per cell the highest depth and the first
+// time with h > h_dry (+inf: never).
+struct MonPtrs {
+    double *mon_rate;
+    double *mon_vol;
+    const int32_t *blk_bnd;
+    double *h_max;
+    double *t_wet;
+};
+
 struct StepArgs {
     // mesh (internal order); block b holds cells [b NC, min((b+1) NC, n))
     const int32_t *blk_edge;
@@ -65,22 +77,16 @@ struct StepArgs {
     // run marks for even and odd step indices (2 x n_blocks); a block runs
     // at step k if it or a neighbour was not quiet for two steps at step
     // k - 1, or if skip_dormant is 0
-    // monitors (all null when off): per boundary slot the outward volume
-    // rate of the last step and the volume since the last reset; per cell
-    // the highest depth and the first time with h > h_dry (+inf: never)
-    double *mon_rate;
-    double *mon_vol;
-    // per block 4 values {first slot, record of the first slot, slots, 0}
-    const int32_t *blk_bnd;
-    double *h_max;
-    double *t_wet;
+    const int32_t *blk_nbr;
+    uint32_t *run;
+    int32_t skip_dormant;
+    // monitors, null when off (read at their point of use, so that their
+    // addresses take no scalar registers through the step)
+    const MonPtrs *mon;
     // ensembles (all null for one mesh): per block its member, with the
     // sign bit set on the member's first block; per member the end of its
     // cell range and its end time; `clock` then points to one clock per
     // member
-    const int32_t *blk_nbr;
-    uint32_t *run;
-    int32_t skip_dormant;
     const int32_t *blk_member;
     const int32_t *member_end;
     const double *t_end_m;

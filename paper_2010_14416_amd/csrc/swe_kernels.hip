@@ -225,11 +225,7 @@ void swe_step_kernel(StepArgs a)
     const int tid = threadIdx.x;
     const int blk = a.blk_base + xcd_block(blockIdx.x, a.n_blocks);
     const int c0 = blk * NC;
-    // dormant blocks: a block that, like each of its neighbour blocks, took
-    // the quiet dry path in the two previous steps has the inputs it had
-    // one step ago, so it would compute (and hold) the same quiet results.
-    // Such a block was not marked to run by any block of the previous step
-    // and returns at once (the clock's block always runs).
+    // run marks of this step's parity
     const size_t run_at = size_t(a.step_index & 1) * size_t(a.n_blocks);
     // one mesh, or member `mem` of an ensemble (its cells start on a block)
     int mem = 0, cell_end = a.n_cells;
@@ -258,7 +254,7 @@ void swe_step_kernel(StepArgs a)
     // the block's boundary slots (discharge monitors), to LDS with phase 1
     int4 bnd = make_int4(0, 0, 0, 0);
     if (MON && tid == NC / 64)
-        bnd = *reinterpret_cast<const int4 *>(a.blk_bnd + 4 * blk);
+        bnd = *reinterpret_cast<const int4 *>(a.mon->blk_bnd + 4 * blk);
     double h = 0.0, hu = 0.0, hv = 0.0, zc = 0.0;
     if (tid < NC && tid < nc_read) {
         h = a.h0[i];
@@ -280,6 +276,12 @@ void swe_step_kernel(StepArgs a)
         ea2 = a.be_a[e0 + tid + NT];
         eb2 = a.be_b[e0 + tid + NT];
     }
+    // dormant blocks: a block that, like each of its neighbour blocks, took
+    // the quiet dry path in the two previous steps has the inputs it had
+    // one step ago, so it would compute (and already holds) the same quiet
+    // results. No block of the previous step marked it to run: it returns
+    // here, its first loads issued (the mark arrives with them; the clock's
+    // block always runs).
     if (a.skip_dormant && !a.store_all && !first && run_me == 0u) return;
     int32_t nbr = -1;   // neighbour blocks, to LDS with phase 1
     if (tid < kNbrSlots) nbr = a.blk_nbr[blk * kNbrSlots + tid];
@@ -487,10 +489,10 @@ void swe_step_kernel(StepArgs a)
     if (MON && owner && hn > hc) {
         // flood envelope: h_max >= h always holds, so the highest depth can
         // only change where the depth rose
-        const double hm = a.h_max[i];
+        const double hm = a.mon->h_max[i];
         if (hn > hm) {
-            a.h_max[i] = hn;
-            if (hm <= h_dry && hn > h_dry) a.t_wet[i] = st.tn;
+            a.mon->h_max[i] = hn;
+            if (hm <= h_dry && hn > h_dry) a.mon->t_wet[i] = st.tn;
         }
     }
     if (MON && s_bnd[0].z > 0) {
@@ -503,8 +505,8 @@ void swe_step_kernel(StepArgs a)
         for (int k = tid; k < b.z; k += NT) {
             const Side pa = decode_side(a.be_a[b.y + k]);
             const double rate = -s_c[pa.k * NC + pa.local];
-            a.mon_rate[b.x + k] = rate;
-            unsafeAtomicAdd(&a.mon_vol[b.x + k], st.dt * rate);
+            a.mon->mon_rate[b.x + k] = rate;
+            unsafeAtomicAdd(&a.mon->mon_vol[b.x + k], st.dt * rate);
         }
     }
 }
@@ -715,7 +717,7 @@ void launch_mon(const StepArgs &a, int schedule, hipStream_t s)
 template <int NC, int NT>
 void launch_one(const StepArgs &a, int schedule, hipStream_t s)
 {
-    if (a.mon_rate)
+    if (a.mon)
         launch_mon<NC, NT, true>(a, schedule, s);
     else
         launch_mon<NC, NT, false>(a, schedule, s);
