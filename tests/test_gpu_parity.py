@@ -375,6 +375,23 @@ def test_monitors_match_the_oracle_and_leave_the_state_alone():
     assert np.all(hm >= s.state()[0])
 
 
+def test_discharge_balance_closes_with_the_ledger():
+    """Mass change = -(volume out through every tag) + mass added by the
+    positivity fix, on the GPU's own monitors, over a run with inflow,
+    fixed stage and wet/dry fronts."""
+    case = W.river(n_target=120_000, workers=1)
+    s = solver(case, params={"monitors": 1})
+    m0, led0, _ = s.diagnostics()
+    s.advance(200)
+    m1, led1, _ = s.diagnostics()
+    t = s.time()[0]
+    out = sum(s.discharge(tag)[1] for tag in (0, 1, 2))
+    q_in = case.bc[1][1]
+    say(f"[balance] dm={m1 - m0!r} out={out!r} ledger={led1 - led0!r}")
+    assert abs(s.discharge(1)[1] + q_in * t) <= 1e-11 * q_in * t
+    assert abs((m1 - m0) - (-out + (led1 - led0))) <= 1e-9 * q_in * t
+
+
 def test_envelope_is_the_running_maximum_of_the_states():
     """Bitwise: the envelope equals the maximum over the run's own states
     (rising, falling and re-rising cells; reading it mid-run changes
