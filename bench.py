@@ -216,6 +216,11 @@ def main():
     ap.add_argument("--no-every-block", action="store_true",
                     help="skip the second timing with every block computed "
                          "and stored (store_all = 1)")
+    ap.add_argument("--wet-band", type=int, default=None,
+                    help="dry cells within this many edge-steps of a wet "
+                         "cell form their own group (swe_set_wet_cells); "
+                         "default: the library's choice (2 from a million "
+                         "cells on, else 0; 2 for ensemble members)")
     ap.add_argument("--no-group-wet", action="store_true",
                     help="order cells along the curve only, without first "
                          "grouping the initially wet cells apart")
@@ -259,7 +264,7 @@ def main():
         bc, bt = int(m.group(1)), int(m.group(2))
         sched, mon, sall = (int(m.group(k) or 0) for k in (3, 4, 5))
         sw = Solver(case, device=0, block_cells=bc,
-                    group_wet=not args.no_group_wet,
+                    group_wet=not args.no_group_wet, wet_band=args.wet_band,
                     params={"block_threads": bt, "load_schedule": sched,
                             "monitors": mon, "store_all": sall})
         sw.advance(args.warmup + 1, want_time=True)
@@ -282,7 +287,7 @@ def main():
 
     t0 = time.perf_counter()
     s = Solver(case, device=0, block_cells=args.block_cells,
-               group_wet=not args.no_group_wet,
+               group_wet=not args.no_group_wet, wet_band=args.wet_band,
                params={"block_threads": args.block_threads})
     info = s.info()
     s.advance(1, want_time=True)          # device set-up + first step
@@ -308,7 +313,7 @@ def main():
     if not args.no_every_block:
         s.close()
         s = Solver(case, device=0, block_cells=args.block_cells,
-                   group_wet=not args.no_group_wet,
+                   group_wet=not args.no_group_wet, wet_band=args.wet_band,
                    params={"block_threads": args.block_threads,
                            "store_all": 1})
         s.advance(args.warmup + 1, want_time=True)
@@ -378,6 +383,7 @@ def run_ensemble(args):
     t1 = time.perf_counter()
     ens = Ensemble(cases, block_cells=args.block_cells,
                    group_wet=not args.no_group_wet,
+                   wet_band=2 if args.wet_band is None else args.wet_band,
                    params={"block_threads": args.block_threads})
     ens.advance(args.warmup)
     ens.time(0)
@@ -402,7 +408,7 @@ def run_ensemble(args):
     solo_ms, solo_cells = [], 0
     for k in pick:
         s = Solver(cases[k], device=0, block_cells=args.block_cells,
-                   group_wet=not args.no_group_wet,
+                   group_wet=not args.no_group_wet, wet_band=args.wet_band,
                    params={"block_threads": args.block_threads})
         s.advance(args.warmup, want_time=True)
         torch.cuda.synchronize()

@@ -164,6 +164,15 @@ swe_status swe_set_mesh(swe_ctx *ctx, int64_t n_nodes, const double *xy,
 swe_status swe_set_cell_groups(swe_ctx *ctx, int64_t n_cells,
                                const uint8_t *group);
 
+/* The same for a wet mask (nonzero: the cell holds water; n_cells values in
+ * user order): three groups, the wet cells, the dry cells at most `band`
+ * edge-steps (0..64) from a wet cell, and the other dry cells. Blocks of
+ * the last group border no wet cell, so they fall dormant (the step skips
+ * them) until water comes within reach. Replaces any groups set before;
+ * used and cleared by the next swe_set_mesh like them. */
+swe_status swe_set_wet_cells(swe_ctx *ctx, int64_t n_cells,
+                             const uint8_t *wet, int32_t band);
+
 /* Counts and sizes of the current mesh. */
 swe_status swe_mesh_info(const swe_ctx *ctx, swe_mesh_stats *out);
 

@@ -456,6 +456,21 @@ swe_status swe_set_cell_groups(swe_ctx *c, int64_t n_cells,
     if (n_cells < 0 || (n_cells > 0 && !group))
         return fail(c, SWE_EINVAL, "null or negative cell groups");
     c->groups.assign(group, group + n_cells);
+    c->wet_band = -1;
+    return SWE_OK;
+}
+
+swe_status swe_set_wet_cells(swe_ctx *c, int64_t n_cells, const uint8_t *wet,
+                             int32_t band)
+{
+    if (!c) return SWE_EINVAL;
+    if (n_cells < 0 || (n_cells > 0 && !wet))
+        return fail(c, SWE_EINVAL, "null or negative wet mask");
+    if (band < 0 || band > 64)
+        return fail(c, SWE_EINVAL, "band must be in [0, 64]");
+    c->groups.resize(size_t(n_cells));
+    for (int64_t k = 0; k < n_cells; ++k) c->groups[k] = wet[k] ? 1 : 0;
+    c->wet_band = n_cells > 0 ? band : -1;
     return SWE_OK;
 }
 
@@ -476,8 +491,10 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t n_nodes, const double *xy,
     const bool ok = swe::build_block_mesh(
         n_nodes, xy, n_cells, tri, n_bnd, bnd_nodes, bnd_tag,
         c->params.block_cells, c->params.reorder != 0,
-        c->groups.empty() ? nullptr : c->groups.data(), SWE_MAX_TAG, m, err);
+        c->groups.empty() ? nullptr : c->groups.data(), c->wet_band,
+        SWE_MAX_TAG, m, err);
     c->groups.clear();
+    c->wet_band = -1;
     if (!ok) return fail(c, SWE_EMESH, err);
     if (c->ws_owned && c->ws) {
         (void)hipSetDevice(c->device);

@@ -48,6 +48,7 @@ struct swe_ctx {
     bool has_mesh = false;
     swe::BlockMesh mesh;
     std::vector<uint8_t> groups;   // cell groups for the next set_mesh
+    int32_t wet_band = -1;         // >= 0: groups is a wet mask
     swe::MonPtrs mon_host{};       // source of the device copy d.mon
     // host copies in internal order; *_dirty: newer than the device copy
     std::vector<double> z, man, h, hu, hv;

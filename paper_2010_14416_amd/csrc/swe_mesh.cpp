@@ -73,8 +73,8 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
                       const int32_t *tri_in, int64_t nbnd,
                       const int32_t *bnd_nodes, const int32_t *bnd_tag,
                       int32_t block_cells, bool reorder,
-                      const uint8_t *group, int32_t max_tag, BlockMesh &M,
-                      std::string &err)
+                      const uint8_t *group, int32_t wet_band,
+                      int32_t max_tag, BlockMesh &M, std::string &err)
 {
     M = BlockMesh();
     if (nn < 3 || nc < 1) {
@@ -379,6 +379,25 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
         // groups in ascending order, each along the curve: with the cells
         // holding water in one group, blocks are wet or dry as a whole
         // except at the seams, and dry blocks cost next to nothing
+        // wet mask to groups: 0 wet, 1 dry within wet_band edge-steps of a
+        // wet cell, 2 beyond (a multi-source breadth-first sweep over edges)
+        std::vector<uint8_t> band_group;
+        if (group && wet_band >= 0) {
+            std::vector<int32_t> dist(nc, INT32_MAX);
+            for (int64_t c = 0; c < nc; ++c)
+                if (group[c]) dist[c] = 0;
+            for (int32_t k = 0; k < wet_band; ++k)
+                for (int64_t e = 0; e < ne; ++e) {
+                    const int32_t l = e_left[e], r = e_right[e];
+                    if (r < 0) continue;
+                    if (dist[l] == k && dist[r] > k + 1) dist[r] = k + 1;
+                    if (dist[r] == k && dist[l] > k + 1) dist[l] = k + 1;
+                }
+            band_group.resize(nc);
+            for (int64_t c = 0; c < nc; ++c)
+                band_group[c] = dist[c] == 0 ? 0 : dist[c] <= wet_band ? 1 : 2;
+            group = band_group.data();
+        }
         if (group) {
             std::vector<int64_t> start(257, 0);
             for (int64_t c = 0; c < nc; ++c) ++start[size_t(group[c]) + 1];

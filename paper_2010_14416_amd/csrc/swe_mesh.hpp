@@ -59,17 +59,19 @@ struct BlockMesh {
 };
 
 // Neighbour blocks kept per block for skipping dormant blocks.
-constexpr int kNbrSlots = 32;
+constexpr int kNbrSlots = 64;
 
 // Builds the block mesh. Returns false and sets err on an invalid mesh.
 // With reorder, cells follow a Hilbert curve through their centroids; with
 // group (one value per cell, or null) too, cells are ordered by group first
-// and along the curve within a group.
+// and along the curve within a group. With wet_band >= 0, group is instead
+// a wet mask and the groups are: wet cells, dry cells at most wet_band
+// edge-steps from a wet cell, the other dry cells.
 bool build_block_mesh(int64_t n_nodes, const double *xy, int64_t n_cells,
                       const int32_t *tri, int64_t n_bnd,
                       const int32_t *bnd_nodes, const int32_t *bnd_tag,
                       int32_t block_cells, bool reorder,
-                      const uint8_t *group, int32_t max_tag, BlockMesh &out,
-                      std::string &err);
+                      const uint8_t *group, int32_t wet_band,
+                      int32_t max_tag, BlockMesh &out, std::string &err);
 
 }  // namespace swe

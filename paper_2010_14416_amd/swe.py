@@ -110,6 +110,9 @@ def load():
                                C.c_int64, _pi32, _pi32]
     L.swe_set_cell_groups.restype = st
     L.swe_set_cell_groups.argtypes = [_p, C.c_int64, C.POINTER(C.c_uint8)]
+    L.swe_set_wet_cells.restype = st
+    L.swe_set_wet_cells.argtypes = [_p, C.c_int64, C.POINTER(C.c_uint8),
+                                    C.c_int32]
     L.swe_mesh_info.restype = st
     L.swe_mesh_info.argtypes = [_p, C.POINTER(swe_mesh_stats)]
     L.swe_get_cell_order.restype = st
@@ -277,6 +280,14 @@ def swe_set_cell_groups(ctx, group):
     g = np.ascontiguousarray(group, dtype=np.uint8).reshape(-1)
     _check(ctx, load().swe_set_cell_groups(
         ctx, g.size, g.ctypes.data_as(C.POINTER(C.c_uint8))))
+
+
+def swe_set_wet_cells(ctx, wet, band=2):
+    """Wet mask (user order) for the next swe_set_mesh: wet cells, dry
+    cells within `band` edge-steps of them, other dry cells."""
+    w = np.ascontiguousarray(wet, dtype=np.uint8).reshape(-1)
+    _check(ctx, load().swe_set_wet_cells(
+        ctx, w.size, w.ctypes.data_as(C.POINTER(C.c_uint8)), int(band)))
 
 
 def swe_mesh_info(ctx):
@@ -519,10 +530,16 @@ class Solver:
     device memory is a torch uint8 tensor bound through swe_bind_workspace;
     with stream="torch" kernels run on torch's current stream. With
     group_wet (and reorder), the cells holding water in the case's state
-    are ordered apart from the dry ones (swe_set_cell_groups)."""
+    are ordered apart from the dry ones, and the dry cells within wet_band
+    edge-steps of them apart from the rest (swe_set_wet_cells). The band
+    lets the far dry blocks fall dormant, at the price of longer records
+    in the seam blocks: it pays on large launches (throughput-bound) and not
+    on small ones, whose step waits for their slowest block; wet_band=None
+    takes 2 from a million cells on, else 0."""
 
     def __init__(self, case, device=0, workspace="torch", stream="torch",
-                 block_cells=256, reorder=True, params=None, group_wet=True):
+                 block_cells=256, reorder=True, params=None, group_wet=True,
+                 wet_band=None):
         self.ctx = swe_create(device)
         self._ws = None
         self.device = device
@@ -536,7 +553,9 @@ class Solver:
                     setattr(p, k, v)
             swe_set_params(self.ctx, p)
             if group_wet and reorder:
-                swe_set_cell_groups(self.ctx, np.where(case.h > p.h_dry, 0, 1))
+                if wet_band is None:
+                    wet_band = 2 if case.n_cells >= 1_000_000 else 0
+                swe_set_wet_cells(self.ctx, case.h > p.h_dry, wet_band)
             swe_set_mesh(self.ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
             for tag, (kind, value) in case.bc.items():
                 swe_set_bc(self.ctx, tag, kind, value)
@@ -609,10 +628,13 @@ class Ensemble:
     workspace / stream are None."""
 
     def __init__(self, cases, device=0, block_cells=256, params=None,
-                 workspace="torch", stream="torch", group_wet=True):
+                 workspace="torch", stream="torch", group_wet=True,
+                 wet_band=2):
+        # one launch for all members: throughput-bound, so the band pays
+        # even on small members
         self.members = [Solver(c, device=device, workspace=None, stream=None,
                                block_cells=block_cells, params=params,
-                               group_wet=group_wet)
+                               group_wet=group_wet, wet_band=wet_band)
                         for c in cases]
         self.n_cells = [c.n_cells for c in cases]
         self.ens = swe_ens_create([m.ctx for m in self.members])

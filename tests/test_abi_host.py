@@ -106,6 +106,33 @@ def test_cell_groups_order_cells_by_group_then_along_the_curve(ctx):
     assert np.array_equal(S.swe_get_cell_order(ctx), curve)
 
 
+def test_wet_cells_order_wet_then_near_dry_then_far_dry(ctx):
+    case = W.river(n_target=40_000, workers=1)
+    wet = case.h > case.h_dry
+    band = 2
+    S.swe_set_wet_cells(ctx, wet, band)
+    S.swe_set_mesh(ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
+    order = S.swe_get_cell_order(ctx)
+    # edge-step distance to the nearest wet cell, by brute force on the
+    # oracle's edge list
+    e = O.Oracle(case).edges()
+    inner = e["right"] >= 0
+    a, b = e["left"][inner], e["right"][inner]
+    dist = np.where(wet, 0, 10**6)
+    for k in range(band):
+        nxt = dist.copy()
+        np.minimum.at(nxt, b, np.where(dist[a] == k, k + 1, 10**6))
+        np.minimum.at(nxt, a, np.where(dist[b] == k, k + 1, 10**6))
+        dist = nxt
+    grp = np.where(dist == 0, 0, np.where(dist <= band, 1, 2))
+    assert np.all(np.diff(grp[np.argsort(order)]) >= 0)
+    assert (grp == 1).sum() > 0 and (grp == 2).sum() > 0
+    # bad band
+    with pytest.raises(S.SweError) as err:
+        S.swe_set_wet_cells(ctx, wet, 65)
+    assert err.value.status == S.SWE_EINVAL
+
+
 def test_cell_groups_of_another_size_are_rejected(ctx):
     case = W.bumps_canal(nx=20, ny=10)
     S.swe_set_cell_groups(ctx, np.zeros(case.n_cells + 1, np.uint8))
