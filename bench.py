@@ -188,7 +188,9 @@ def main():
                     choices=["river", "bumps", "canal", "ensemble",
                              "adjoint"])
     ap.add_argument("--cells", type=int, default=13_000_000)
-    ap.add_argument("--block-cells", type=int, default=256)
+    ap.add_argument("--block-cells", type=int, default=None,
+                    help="cells per block (default: 256; 128 for the "
+                         "ensemble, whose members run alone keep 256)")
     ap.add_argument("--block-threads", type=int, default=0,
                     help="0: automatic (= block cells)")
     ap.add_argument("--workers", type=int,
@@ -286,7 +288,7 @@ def main():
         del sw
 
     t0 = time.perf_counter()
-    s = Solver(case, device=0, block_cells=args.block_cells,
+    s = Solver(case, device=0, block_cells=args.block_cells or 256,
                group_wet=not args.no_group_wet, wet_band=args.wet_band,
                params={"block_threads": args.block_threads})
     info = s.info()
@@ -312,7 +314,7 @@ def main():
     every_ms = None
     if not args.no_every_block:
         s.close()
-        s = Solver(case, device=0, block_cells=args.block_cells,
+        s = Solver(case, device=0, block_cells=args.block_cells or 256,
                    group_wet=not args.no_group_wet, wet_band=args.wet_band,
                    params={"block_threads": args.block_threads,
                            "store_all": 1})
@@ -381,7 +383,7 @@ def run_ensemble(args):
     log(f"ensemble: {len(cases)} members, {n} cells "
         f"({time.perf_counter() - t0:.1f} s to generate)")
     t1 = time.perf_counter()
-    ens = Ensemble(cases, block_cells=args.block_cells,
+    ens = Ensemble(cases, block_cells=args.block_cells or 128,
                    group_wet=not args.no_group_wet,
                    wet_band=2 if args.wet_band is None else args.wet_band,
                    params={"block_threads": args.block_threads})
@@ -407,7 +409,7 @@ def run_ensemble(args):
     pick = np.linspace(0, len(cases) - 1, k_sample).round().astype(int)
     solo_ms, solo_cells = [], 0
     for k in pick:
-        s = Solver(cases[k], device=0, block_cells=args.block_cells,
+        s = Solver(cases[k], device=0, block_cells=args.block_cells or 256,
                    group_wet=not args.no_group_wet, wet_band=args.wet_band,
                    params={"block_threads": args.block_threads})
         s.advance(args.warmup, want_time=True)
