@@ -159,8 +159,9 @@ swe_status swe_set_mesh(swe_ctx *ctx, int64_t n_nodes, const double *xy,
  * group. n_cells values in user order (copied; n_cells = 0 clears them); the
  * next swe_set_mesh uses and clears them, and fails with SWE_EINVAL if its
  * cell count differs. Grouping the cells that hold water at the start apart
- * from the dry ones makes blocks wet or dry as a whole, and a dry block
- * costs next to nothing; results do not depend on the order. */
+ * from the dry ones makes blocks wet or dry as a whole: a dry block costs
+ * little, and one that borders no changing block is skipped (dormant).
+ * Results do not depend on the order; only the speed does. */
 swe_status swe_set_cell_groups(swe_ctx *ctx, int64_t n_cells,
                                const uint8_t *group);
 
