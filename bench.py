@@ -350,6 +350,13 @@ def main():
         log(f"cpu baseline: oracle on {threads} threads")
         base = cpu_baseline(case, args.cpu_seconds, threads)
         log(f"cpu baseline {base['value']:.3e} cell-updates/s")
+        if threads > 1:
+            # the same oracle on one core, a shorter sample
+            one = cpu_baseline(case, min(10.0, args.cpu_seconds), 1)
+            base["single_core_value"] = one["value"]
+            base["single_core_sample"] = one["sample"]
+            log(f"cpu baseline, one core: {one['value']:.3e} "
+                f"cell-updates/s")
 
     out = dict(
         metric=METRIC, value=value, unit="cell-updates/s", n_gpus=1,
