@@ -160,7 +160,7 @@ def two_triangles():
 
 @pytest.mark.parametrize("kind", ["degenerate", "range", "nonmanifold",
                                   "overlap", "segment", "dupseg", "tag",
-                                  "repeat", "nan"])
+                                  "repeat", "nan", "empty"])
 def test_mesh_errors(ctx, kind):
     xy, tri = two_triangles()
     bnd = tag = None
@@ -186,6 +186,8 @@ def test_mesh_errors(ctx, kind):
         tri[1] = [0, 2, 2]
     elif kind == "nan":
         xy[3, 0] = np.nan
+    elif kind == "empty":
+        tri = np.zeros((0, 3), np.int32)
     with pytest.raises(S.SweError) as e:
         S.swe_set_mesh(ctx, xy, tri, bnd, tag)
     assert e.value.status == S.SWE_EMESH

@@ -220,6 +220,30 @@ def test_user_cell_permutation_gives_identical_bits():
         assert np.array_equal(x[perm], y)
 
 
+def test_zero_steps_change_nothing():
+    """advance(0) and a zero-length frozen schedule are no-ops, also
+    after steps (dormant marks and clock untouched)."""
+    from paper_2010_14416_amd import swe as S
+    case = W.bumps_canal(nx=60, ny=20, lx=30.0, ly=10.0, x_dam=10.0)
+    s = solver(case)
+    s.advance(0)
+    assert s.time()[0] == 0.0
+    for x, y in zip(s.state(), (case.h, case.hu, case.hv)):
+        assert np.array_equal(x, y)
+    s.advance(30)
+    before, t = s.state(), s.time()
+    s.advance(0)
+    S.swe_advance_dt(s.ctx, 0, np.zeros(0))
+    assert s.time() == t
+    for x, y in zip(s.state(), before):
+        assert np.array_equal(x, y)
+    ref = solver(case)
+    ref.advance(60)
+    s.advance(30)
+    for x, y in zip(s.state(), ref.state()):
+        assert np.array_equal(x, y)
+
+
 def test_run_to_run_determinism():
     case = W.river(n_target=50_000, workers=1)
     a = solver(case)
