@@ -78,6 +78,26 @@ def test_dormant_blocks_change_no_member_bit():
         assert a.time(k) == b.time(k)
 
 
+def test_full_size_ensemble_sampled_members_match_their_own_runs():
+    """The benchmarked configuration (256 members, 27.7 M cells, the
+    Ensemble's defaults): sampled members after 100 steps equal, bit for
+    bit, their own runs with the Solver's defaults."""
+    from paper_2010_14416_amd import Ensemble
+    cases = W.ensemble_members(steps=100)
+    say(f"[ensemble full] {len(cases)} members, "
+        f"{sum(c.n_cells for c in cases)} cells")
+    ens = Ensemble(cases)
+    ens.advance(100)
+    for k in (0, 57, 128, 255):
+        (h, hu, hv), (t, dt, step) = solo(cases[k], 100)
+        eh, ehu, ehv = ens.state(k)
+        say(f"  member {k}: {cases[k].n_cells} cells, t={t!r}")
+        assert np.array_equal(eh, h) and np.array_equal(ehu, hu)
+        assert np.array_equal(ehv, hv)
+        assert ens.time(k) == (t, dt, step)
+    ens.close()
+
+
 def test_members_stop_at_their_own_end_times():
     from paper_2010_14416_amd import Ensemble
     cases = members()[:4]
