@@ -227,6 +227,7 @@ void swe_step_kernel(StepArgs a)
     const int c0 = blk * NC;
     // run marks of this step's parity
     const size_t run_at = size_t(a.step_index & 1) * size_t(a.n_blocks);
+    const uint32_t run_me = a.run[run_at + blk];
     // one mesh, or member `mem` of an ensemble (its cells start on a block)
     int mem = 0, cell_end = a.n_cells;
     bool first = blk == 0;
@@ -236,6 +237,12 @@ void swe_step_kernel(StepArgs a)
         mem = code & 0x7fffffff;
         cell_end = a.member_end[mem];
     }
+    // dormant blocks: a block that, like each of its neighbour blocks, took
+    // the quiet dry path in the two previous steps has the inputs it had
+    // one step ago, so it would compute (and already holds) the same quiet
+    // results. No block of the previous step marked it to run: it returns
+    // before any other load (the clock's block always runs).
+    if (a.skip_dormant && !a.store_all && !first && run_me == 0u) return;
     Clock *clock = a.clock + mem;
     const double t_end = a.t_end_m ? a.t_end_m[mem] : a.t_end;
     const int nc = min(NC, cell_end - c0);
@@ -250,7 +257,6 @@ void swe_step_kernel(StepArgs a)
 
     // phase 1: owned cell, first edge record (+ geometry), neighbour state
     const int quiet_steps = a.quiet[blk];
-    const uint32_t run_me = a.run[run_at + blk];
     // the block's boundary slots (discharge monitors), to LDS with phase 1
     int4 bnd = make_int4(0, 0, 0, 0);
     if (MON && tid == NC / 64)
@@ -276,13 +282,6 @@ void swe_step_kernel(StepArgs a)
         ea2 = a.be_a[e0 + tid + NT];
         eb2 = a.be_b[e0 + tid + NT];
     }
-    // dormant blocks: a block that, like each of its neighbour blocks, took
-    // the quiet dry path in the two previous steps has the inputs it had
-    // one step ago, so it would compute (and already holds) the same quiet
-    // results. No block of the previous step marked it to run: it returns
-    // here, its first loads issued (the mark arrives with them; the clock's
-    // block always runs).
-    if (a.skip_dormant && !a.store_all && !first && run_me == 0u) return;
     int32_t nbr = -1;   // neighbour blocks, to LDS with phase 1
     if (tid < kNbrSlots) nbr = a.blk_nbr[blk * kNbrSlots + tid];
     // the momentum of a dry cell is read in phase 3, and only if needed
