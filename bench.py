@@ -189,7 +189,7 @@ def main():
                              "adjoint"])
     ap.add_argument("--cells", type=int, default=13_000_000)
     ap.add_argument("--block-cells", type=int, default=None,
-                    help="cells per block (default: 256; 128 for the "
+                    help="cells per block (default: 256; 64 for the "
                          "ensemble, whose members run alone keep 256)")
     ap.add_argument("--block-threads", type=int, default=0,
                     help="0: automatic (= block cells)")
@@ -390,7 +390,7 @@ def run_ensemble(args):
     log(f"ensemble: {len(cases)} members, {n} cells "
         f"({time.perf_counter() - t0:.1f} s to generate)")
     t1 = time.perf_counter()
-    ens = Ensemble(cases, block_cells=args.block_cells or 128,
+    ens = Ensemble(cases, block_cells=args.block_cells or 64,
                    group_wet=not args.no_group_wet,
                    wet_band=2 if args.wet_band is None else args.wet_band,
                    params={"block_threads": args.block_threads})

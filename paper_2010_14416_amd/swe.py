@@ -627,12 +627,12 @@ class Ensemble:
     torch uint8 tensor and kernels run on torch's current stream, unless
     workspace / stream are None."""
 
-    def __init__(self, cases, device=0, block_cells=128, params=None,
+    def __init__(self, cases, device=0, block_cells=64, params=None,
                  workspace="torch", stream="torch", group_wet=True,
                  wet_band=2):
         # one launch for all members: throughput-bound, so the band pays
-        # even on small members, and 128-cell blocks (finer dormant blocks
-        # on coarse member meshes) beat 256-cell ones
+        # even on small members, and 64-cell blocks (finer dormant blocks
+        # on coarse member meshes) beat 128- and 256-cell ones
         self.members = [Solver(c, device=device, workspace=None, stream=None,
                                block_cells=block_cells, params=params,
                                group_wet=group_wet, wet_band=wet_band)
