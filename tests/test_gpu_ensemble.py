@@ -62,6 +62,25 @@ def test_members_match_their_own_runs_bitwise():
         assert (et, edt, estep) == (t, dt, step)
 
 
+@pytest.mark.parametrize("block_cells", [128, 256])
+def test_other_block_sizes_match_their_own_runs_bitwise(block_cells):
+    """The ragged mix with 128- and 256-cell ensemble blocks (the default is
+    64): each member after 120 steps equals, bit for bit, its own run with
+    the Solver's defaults."""
+    from paper_2010_14416_amd import Ensemble
+    cases = members()
+    ens = Ensemble(cases, block_cells=block_cells)
+    ens.advance(120)
+    for k, case in enumerate(cases):
+        (h, hu, hv), (t, dt, step) = solo(case, 120)
+        eh, ehu, ehv = ens.state(k)
+        say(f"  [{block_cells}] member {k} {case.name}: t={t!r}")
+        assert np.array_equal(eh, h) and np.array_equal(ehu, hu)
+        assert np.array_equal(ehv, hv)
+        assert ens.time(k) == (t, dt, step)
+    ens.close()
+
+
 def test_dormant_blocks_change_no_member_bit():
     """The ensemble with dormant-block skipping and store skipping (the
     default) against the ensemble with both off (store_all = 1), over a run
