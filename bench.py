@@ -240,8 +240,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build's hot path has no "
-              f"multi-GPU decomposition (asked for --gpus {args.gpus}).",
+        print(f"bench.py runs on one GPU only: the step has no multi-GPU "
+              f"decomposition (asked for --gpus {args.gpus}).",
               file=sys.stderr, flush=True)
         sys.exit(2)
 

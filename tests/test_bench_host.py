@@ -1,0 +1,63 @@
+"""Host logic of bench.py (no GPU): the one-GPU refusal, the counter
+summary's copy-kernel calibration, and the rule that measured traffic is
+reported only for the kernel source and workload size it was taken on."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"),
+                        "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
+
+
+def _counter_csv(path, counter, rows):
+    with open(path, "w") as f:
+        f.write("Kernel_Name,Counter_Name,Counter_Value\n")
+        for name, value in rows:
+            f.write(f'"{name}",{counter},{value}\n')
+
+
+def test_pmc_summary_scales_by_the_copy_kernel(tmp_path):
+    """A 1 MiB copy kernel reads as 512 KiB FETCH_SIZE and 1 024 KiB
+    WRITE_SIZE: fetch counts are doubled, write counts kept."""
+    step = "void swe::swe_step_kernel<256, 256, false, false>(swe::StepArgs)"
+    neg = "at::native::vectorized_elementwise_kernel<neg_kernel_cuda>"
+    f, w = tmp_path / "f.csv", tmp_path / "w.csv"
+    _counter_csv(f, "FETCH_SIZE", [(neg, 512.0), (step, 100.0),
+                                   (step, 300.0)])
+    _counter_csv(w, "WRITE_SIZE", [(neg, 1024.0), (step, 50.0)])
+    out = tmp_path / "t.json"
+    bench.pmc_summary(str(f), str(w), 1, 1000, str(out))
+    t = json.loads(out.read_text())
+    assert t["reference"]["fetch_scale"] == 2.0
+    assert t["reference"]["write_scale"] == 1.0
+    assert t["fetch_bytes_per_launch"] == 200.0 * 1024 * 2.0
+    assert t["write_bytes_per_launch"] == 50.0 * 1024
+    assert t["bytes_per_cell"] == (200.0 * 2048 + 50.0 * 1024) / 1000
+    assert t["dispatches"] == {"fetch": 2, "write": 1}
+    assert t["kernel_sha256"] == bench.kernel_hash()
+
+
+def test_traffic_only_for_its_kernel_and_size(tmp_path, monkeypatch):
+    path = tmp_path / "t.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
+    assert bench.traffic_per_launch("river", 10) is None   # no file
+    path.write_text(json.dumps(dict(kernel_sha256=bench.kernel_hash(),
+                                    n_cells=10, bytes_per_launch=123.0)))
+    assert bench.traffic_per_launch("river", 10) == 123.0
+    assert bench.traffic_per_launch("river", 11) is None   # other size
+    path.write_text(json.dumps(dict(kernel_sha256="0" * 64, n_cells=10,
+                                    bytes_per_launch=123.0)))
+    assert bench.traffic_per_launch("river", 10) is None   # other source
