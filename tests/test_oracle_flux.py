@@ -326,3 +326,102 @@ def test_fixed_depth_with_cell_depth_equals_transmissive():
     assert rel(cf, ct) < 1e-14
     cs = O.boundary_edge(4, 0.9 + 0.25, 0.0, U, 0.25, n, 1.0)
     assert rel(cs, ct) < 1e-14
+
+
+# ----------------------------------------- fixed depth / fixed stage (R16)
+# The downstream level is held by a ghost cell outside the boundary edge: it
+# has the prescribed depth (or the depth of the prescribed surface above the
+# cell's bed) and the cell's own velocity, and the edge flux is the Riemann
+# flux between the cell (inside, left of the outward normal) and the ghost.
+
+def rotated(cl, n, L):
+    """Flux (G0, G1, G2) in the edge frame from a contribution cl = -L F."""
+    F0, F1, F2 = -cl[0] / L, -cl[1] / L, -cl[2] / L
+    return np.array([F0, F1 * n[0] + F2 * n[1], -F1 * n[1] + F2 * n[0]])
+
+
+def ghost_cases(seed, n=400):
+    """Cell states with oblique velocities, ghost depths above and below."""
+    rng = np.random.default_rng(seed)
+    for _ in range(n):
+        h = rng.uniform(0.1, 3.0)
+        u, v = rng.normal(0, 1.0, 2)
+        hb = h * rng.uniform(0.3, 2.5)
+        th = rng.uniform(0, 2 * np.pi)
+        yield h, u, v, hb, np.array([np.cos(th), np.sin(th)])
+
+
+def test_fixed_depth_ghost_is_the_outer_neighbour():
+    """On a flat bed the boundary edge equals, exactly, an interior edge
+    whose right (outer) cell holds the ghost (h_b, h_b u, h_b v): the ghost
+    sits outside, beyond the outward normal, and moves with the cell."""
+    inflow = outflow = 0
+    for h, u, v, hb, n in ghost_cases(11):
+        L = 1.7
+        cb = O.boundary_edge(3, hb, 0.0, [h, h * u, h * v], 0.4, n, L)
+        ci, _ = O.interior_edge([h, h * u, h * v], 0.4,
+                                [hb, hb * u, hb * v], 0.4, n, L)
+        # the interior edge recovers u = (h_b u) / h_b, which may round
+        assert rel(cb, ci) < 1e-14
+        inflow += cb[0] > 0
+        outflow += cb[0] < 0
+    assert inflow > 50 and outflow > 50   # both directions exercised
+
+
+def test_fixed_stage_ghost_depth_is_stage_minus_bed():
+    """A fixed surface elevation s over a cell of bed z is the fixed depth
+    s - z, and a stage below the bed leaves a dry ghost (depth 0)."""
+    rng = np.random.default_rng(12)
+    for h, u, v, hb, n in ghost_cases(13, 200):
+        z = rng.uniform(-2.0, 2.0)
+        U = [h, h * u, h * v]
+        cs = O.boundary_edge(4, z + hb, 0.0, U, z, n, 1.3)
+        cd = O.boundary_edge(3, hb, 0.0, U, z, n, 1.3)
+        assert rel(cs, cd) < 1e-14
+        cdry = O.boundary_edge(4, z - 0.5, 0.0, U, z, n, 1.3)
+        assert np.array_equal(cdry, O.boundary_edge(3, 0.0, 0.0, U, z, n,
+                                                    1.3))
+        ci, _ = O.interior_edge(U, z, [0.0, 0.0, 0.0], z, n, 1.3)
+        assert np.array_equal(cdry, ci)
+
+
+@pytest.mark.parametrize("kind", [3, 4])
+def test_deeper_ghost_fills_and_shallower_drains_a_still_cell(kind):
+    """Water at rest next to a higher held level flows in, next to a lower
+    one flows out. For mild level differences the rate is that of the exact
+    Godunov flux of the dam break between the two (HLLC tracks it to 5 %
+    there; for strong ones only the direction is checked)."""
+    n = np.array([0.6, -0.8])
+    L = 2.0
+    z = 0.3
+    cases = [(1.0, 1.2, True), (1.0, 0.8, True), (1.0, 1.05, True),
+             (2.0, 1.7, True), (0.5, 0.6, True), (0.4, 2.0, False),
+             (1.5, 0.2, False), (0.8, 0.0, False)]
+    for h, hb, mild in cases:
+        value = hb if kind == 3 else z + hb
+        cl = O.boundary_edge(kind, value, 0.0, [h, 0.0, 0.0], z, n, L)
+        G = rotated(cl, n, L)
+        # outward mass flux: negative (inflow) iff the ghost is deeper
+        assert (G[0] < 0) == (hb > h) and G[0] != 0.0
+        if mild:
+            Ge = [float(x) for x in godunov_flux(h, 0.0, 0.0, hb, 0.0, 0.0)]
+            assert abs(G[0] - Ge[0]) <= 0.05 * abs(Ge[0])
+            assert abs(G[1] - Ge[1]) <= 0.05 * abs(Ge[1])
+
+
+@pytest.mark.parametrize("kind", [3, 4])
+def test_ghost_carries_the_cell_tangential_velocity(kind):
+    """Both sides of the held-level Riemann problem move along the edge with
+    the cell's tangential velocity u_t, so whatever the direction of the
+    flow the tangential momentum flux is the mass flux times u_t (exactly so
+    in the Godunov flux, where u_t is carried by the contact)."""
+    seen_in = 0
+    for h, u, v, hb, n in ghost_cases(14):
+        z = 0.2
+        value = hb if kind == 3 else z + hb
+        cl = O.boundary_edge(kind, value, 0.0, [h, h * u, h * v], z, n, 1.0)
+        G = rotated(cl, n, 1.0)
+        ut = -u * n[1] + v * n[0]
+        assert abs(G[2] - G[0] * ut) <= 1e-13 * max(1.0, abs(G[0] * ut))
+        seen_in += G[0] < -1e-3 and abs(ut) > 0.1
+    assert seen_in > 30

@@ -74,6 +74,16 @@ PLANTED = {
     # velocity of the right cell taken from the left one
     "velocity_index": ("velocity(h_dry, hj, huj, hvj, &uj, &vj);",
                        "velocity(h_dry, hi, huj, hvj, &uj, &vj);"),
+    # fixed depth: ghost placed inside (left of the outward normal)
+    "ghost_left_depth": ("ora_hllc(g, h_dry, hi, un, ut, value, un, ut, G);",
+                         "ora_hllc(g, h_dry, value, un, ut, hi, un, ut, G);"),
+    # fixed stage: ghost placed inside
+    "ghost_left_stage": ("ora_hllc(g, h_dry, hi, un, ut, hb, un, ut, G);",
+                         "ora_hllc(g, h_dry, hb, un, ut, hi, un, ut, G);"),
+    # fixed depth: ghost at rest along the edge
+    "ghost_zero_tangential": (
+        "ora_hllc(g, h_dry, hi, un, ut, value, un, ut, G);",
+        "ora_hllc(g, h_dry, hi, un, ut, value, un, 0.0, G);"),
     # monitors: inward instead of outward rate
     "monitor_rate_sign": ("o->brate[e] = -o->cl[3 * e];",
                           "o->brate[e] = o->cl[3 * e];"),
