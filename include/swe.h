@@ -154,6 +154,31 @@ swe_status swe_set_mesh(swe_ctx *ctx, int64_t n_nodes, const double *xy,
                         int64_t n_cells, const int32_t *tri, int64_t n_bnd,
                         const int32_t *bnd_nodes, const int32_t *bnd_tag);
 
+/* The same mesh with its edges given (sec. 3.1: the finite volumes are the
+ * triangles, and the fluxes cross their edges; the mesh is the node
+ * coordinates, the triangles, the edge-to-cell connectivity and the tags of
+ * the boundary edges). n_edges edges: edge_nodes[2*e], edge_nodes[2*e+1]
+ * (either order), edge_cells[2*e], edge_cells[2*e+1] (the one or two
+ * triangles on the edge, in either slot; -1 in the other slot on the
+ * boundary), edge_tag[e] (the boundary condition tag of a boundary edge, in
+ * [0, SWE_MAX_TAG); 0 on interior edges; NULL: every tag 0). Arrays are
+ * caller-owned and copied. The list is validated against the triangles:
+ * SWE_EMESH for a node or triangle index out of range, an edge that is not
+ * a side of a triangle it names, a triangle side on no listed edge or on
+ * two, two edges joining the same nodes, two triangles on the same side of
+ * an edge, a tag out of range or nonzero on an interior edge, and every
+ * defect swe_set_mesh reports for the triangles. The edges are used as
+ * given (no edge search); left/right and normals follow the same rule as
+ * swe_set_mesh (left: the triangle whose counter-clockwise boundary runs
+ * from the lower to the higher node number), so a run is bitwise that of
+ * swe_set_mesh with the boundary edges listed as tagged segments. Resets
+ * the context as swe_set_mesh does. */
+swe_status swe_set_mesh_edges(swe_ctx *ctx, int64_t n_nodes, const double *xy,
+                              int64_t n_cells, const int32_t *tri,
+                              int64_t n_edges, const int32_t *edge_nodes,
+                              const int32_t *edge_cells,
+                              const int32_t *edge_tag);
+
 /* Cell groups for the next swe_set_mesh (with reorder = 1): cells are
  * ordered by group value first and along the space-filling curve within a
  * group. n_cells values in user order (copied; n_cells = 0 clears them); the
@@ -176,6 +201,12 @@ swe_status swe_set_wet_cells(swe_ctx *ctx, int64_t n_cells,
 
 /* Counts and sizes of the current mesh. */
 swe_status swe_mesh_info(const swe_ctx *ctx, swe_mesh_stats *out);
+
+/* 64-bit digest (FNV-1a) of the internal mesh the step reads: cell order,
+ * areas, inscribed radii, block edge records, normals, lengths, boundary
+ * slots and tags, neighbour blocks. Two ways of giving the same mesh (edges
+ * discovered or listed) yield the same digest. Host only. */
+swe_status swe_mesh_digest(const swe_ctx *ctx, uint64_t *digest);
 
 /* internal_of_user[c] = position of user cell c in the library's internal
  * (locality) order. */
@@ -202,7 +233,10 @@ swe_status swe_set_manning(swe_ctx *ctx, const double *n, swe_mem mem);
 swe_status swe_set_state(swe_ctx *ctx, const double *h, const double *hu,
                          const double *hv, swe_mem mem);
 
-/* Copies the current state out (user order) and synchronises the stream. */
+/* Copies the current state out (user order) and synchronises the stream.
+ * Returns SWE_ENUMERIC (the state is still copied out) if a step since the
+ * clock was last set produced a non-finite state or an unbounded time step,
+ * so that an error deferred by an asynchronous swe_advance surfaces here. */
 swe_status swe_get_state(swe_ctx *ctx, double *h, double *hu, double *hv,
                          swe_mem mem);
 
@@ -221,7 +255,10 @@ swe_status swe_get_time(swe_ctx *ctx, double *t, double *last_dt,
  * *steps_done and *t_now (either may be NULL) are exact after a sync; with
  * t_end = INFINITY they are max_steps and a synchronised time. Returns
  * SWE_ENUMERIC if a step produced a non-finite state or an unbounded time
- * step (all cells dry, dt_max and t_end infinite). */
+ * step (all cells dry, dt_max and t_end infinite); with t_end = INFINITY
+ * and t_now NULL the call does not wait for the steps, and the error is
+ * reported by the next call that synchronises (swe_get_state,
+ * swe_get_time, swe_get_diagnostics, or the next swe_advance). */
 swe_status swe_advance(swe_ctx *ctx, int64_t max_steps, double t_end,
                        int64_t *steps_done, double *t_now);
 
@@ -262,7 +299,8 @@ swe_status swe_adjoint_gauges(swe_ctx *ctx, int64_t steps, int32_t n_gauges,
 
 /* Total water volume sum |Omega_i| h_i [m^3], the volume added by the
  * positivity fix since the mesh was set [m^3], and the number of cells
- * with h > h_dry. Synchronises the stream. */
+ * with h > h_dry. Synchronises the stream; returns SWE_ENUMERIC (values
+ * still written) after a failed step, as swe_get_state. */
 swe_status swe_get_diagnostics(swe_ctx *ctx, double *mass, double *ledger,
                                int64_t *n_wet);
 

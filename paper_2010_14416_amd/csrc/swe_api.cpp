@@ -281,6 +281,15 @@ swe_status read_clock(swe_ctx *c, Clock *out)
     return SWE_OK;
 }
 
+// Reads the device clock (synchronising the stream) and reports a step
+// that raised its health word since the clock was last set: the results a
+// caller reads after such a step are not those of a valid run.
+swe_status check_health(swe_ctx *c)
+{
+    Clock ck;
+    return read_clock(c, &ck);
+}
+
 swe_status check_flag(swe_ctx *c, bool *bad)
 {
     unsigned f = 0;
@@ -331,8 +340,11 @@ swe_status set_field(swe_ctx *c, const double *src, swe_mem mem, Field f)
     if (f == Field::manning)
         HIPCHK(c, swe::launch_gm2(c->d.man, c->d.gm2, nc, c->params.g,
                                   c->stream));
+    // an input of the step changed: no block may be taken as dormant (a
+    // lowered bed under a fixed stage, say, must start inflow)
+    c->quiet_dirty = true;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return SWE_OK;
+    return prepare(c);
 }
 
 }  // namespace
@@ -474,13 +486,18 @@ swe_status swe_set_wet_cells(swe_ctx *c, int64_t n_cells, const uint8_t *wet,
     return SWE_OK;
 }
 
-swe_status swe_set_mesh(swe_ctx *c, int64_t n_nodes, const double *xy,
-                        int64_t n_cells, const int32_t *tri, int64_t n_bnd,
-                        const int32_t *bnd_nodes, const int32_t *bnd_tag)
+}  // extern "C"
+
+namespace {
+
+// Common part of swe_set_mesh and swe_set_mesh_edges: builds the block mesh
+// (edges discovered from the triangles with boundary segments, or taken
+// from the caller's edge list) and resets the context to it.
+swe_status set_mesh_common(swe_ctx *c, int64_t n_nodes, const double *xy,
+                           int64_t n_cells, const int32_t *tri, int64_t n_bnd,
+                           const int32_t *bnd_nodes, const int32_t *bnd_tag,
+                           const swe::EdgeInput *edges)
 {
-    if (!c) return SWE_EINVAL;
-    if (!xy || !tri || n_bnd < 0 || (n_bnd > 0 && (!bnd_nodes || !bnd_tag)))
-        return fail(c, SWE_EINVAL, "null mesh array");
     if (!c->groups.empty() && int64_t(c->groups.size()) != n_cells) {
         c->groups.clear();
         return fail(c, SWE_EINVAL,
@@ -492,7 +509,7 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t n_nodes, const double *xy,
         n_nodes, xy, n_cells, tri, n_bnd, bnd_nodes, bnd_tag,
         c->params.block_cells, c->params.reorder != 0,
         c->groups.empty() ? nullptr : c->groups.data(), c->wet_band,
-        SWE_MAX_TAG, m, err);
+        SWE_MAX_TAG, m, err, edges);
     c->groups.clear();
     c->wet_band = -1;
     if (!ok) return fail(c, SWE_EMESH, err);
@@ -523,6 +540,40 @@ swe_status swe_set_mesh(swe_ctx *c, int64_t n_nodes, const double *xy,
     return SWE_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+swe_status swe_set_mesh(swe_ctx *c, int64_t n_nodes, const double *xy,
+                        int64_t n_cells, const int32_t *tri, int64_t n_bnd,
+                        const int32_t *bnd_nodes, const int32_t *bnd_tag)
+{
+    if (!c) return SWE_EINVAL;
+    if (!xy || !tri || n_bnd < 0 || (n_bnd > 0 && (!bnd_nodes || !bnd_tag)))
+        return fail(c, SWE_EINVAL, "null mesh array");
+    return set_mesh_common(c, n_nodes, xy, n_cells, tri, n_bnd, bnd_nodes,
+                           bnd_tag, nullptr);
+}
+
+swe_status swe_set_mesh_edges(swe_ctx *c, int64_t n_nodes, const double *xy,
+                              int64_t n_cells, const int32_t *tri,
+                              int64_t n_edges, const int32_t *edge_nodes,
+                              const int32_t *edge_cells,
+                              const int32_t *edge_tag)
+{
+    if (!c) return SWE_EINVAL;
+    if (!xy || !tri || n_edges < 0 ||
+        (n_edges > 0 && (!edge_nodes || !edge_cells)))
+        return fail(c, SWE_EINVAL, "null mesh array");
+    swe::EdgeInput in;
+    in.n = n_edges;
+    in.nodes = edge_nodes;
+    in.cells = edge_cells;
+    in.tag = edge_tag;
+    return set_mesh_common(c, n_nodes, xy, n_cells, tri, 0, nullptr, nullptr,
+                           &in);
+}
+
 swe_status swe_mesh_info(const swe_ctx *c, swe_mesh_stats *o)
 {
     if (!c || !o) return SWE_EINVAL;
@@ -538,6 +589,40 @@ swe_status swe_mesh_info(const swe_ctx *c, swe_mesh_stats *o)
     o->max_block_edges = m.max_block_edges;
     o->min_inradius = m.min_inradius;
     o->total_area = m.total_area;
+    return SWE_OK;
+}
+
+swe_status swe_mesh_digest(const swe_ctx *c, uint64_t *digest)
+{
+    if (!c || !digest) return SWE_EINVAL;
+    if (!c->has_mesh) return SWE_ENOTREADY;
+    // FNV-1a over the bytes of every array the step kernel reads
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](const void *p, size_t n) {
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        for (size_t k = 0; k < n; ++k) {
+            h ^= b[k];
+            h *= 1099511628211ull;
+        }
+    };
+    const BlockMesh &m = c->mesh;
+    auto vec = [&mix](const auto &v) {
+        mix(v.data(), v.size() * sizeof(v[0]));
+    };
+    vec(m.internal_of_user);
+    vec(m.area);
+    vec(m.inradius);
+    vec(m.blk_edge);
+    vec(m.be_a);
+    vec(m.be_b);
+    vec(m.be_nx);
+    vec(m.be_ny);
+    vec(m.be_len);
+    vec(m.bnd_tag);
+    vec(m.blk_bnd);
+    vec(m.blk_nbr);
+    vec(m.tag_length);
+    *digest = h;
     return SWE_OK;
 }
 
@@ -648,8 +733,7 @@ swe_status swe_get_state(swe_ctx *c, double *h, double *hu, double *hv,
         HIPCHK(c, swe::launch_gather3(c->d.h[b], c->d.hu[b], c->d.hv[b], h,
                                       hu, hv, c->d.internal_of_user, nc,
                                       c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        return SWE_OK;
+        return check_health(c);
     }
     if (mem != SWE_MEM_HOST) return fail(c, SWE_EINVAL, "bad memory kind");
     std::vector<double> a(nc), bb(nc), cc(nc);
@@ -666,7 +750,7 @@ swe_status swe_get_state(swe_ctx *c, double *h, double *hu, double *hv,
         hu[u] = bb[i];
         hv[u] = cc[i];
     }
-    return SWE_OK;
+    return check_health(c);
 }
 
 swe_status swe_set_time(swe_ctx *c, double t, int64_t step)
@@ -960,7 +1044,7 @@ swe_status swe_get_diagnostics(swe_ctx *c, double *mass, double *ledger,
     if (mass) *mass = s;
     if (ledger) *ledger = l;
     if (n_wet) *n_wet = int64_t(w);
-    return SWE_OK;
+    return check_health(c);
 }
 
 swe_status swe_reset_monitors(swe_ctx *c)

@@ -122,9 +122,13 @@ __device__ __forceinline__ int block_finish(const StepArgs &a, int blk,
         if (first) {
             const int nn = nxt == 2 ? 0 : nxt + 1;
             clock->t[nxt] = tn;
-            clock->last_dt = dt;
             clock->dt_ring[a.step_index & 7] = dt;
-            if (dt > 0.0) clock->steps += 1;
+            // the empty steps launched after t_end leave the last time
+            // step and the step count alone
+            if (dt > 0.0) {
+                clock->last_dt = dt;
+                clock->steps += 1;
+            }
             for (int x = 0; x < kClockLanes; ++x)
                 atomicExch(&clock->minrs[nn][x][0], kInfBits);
         }

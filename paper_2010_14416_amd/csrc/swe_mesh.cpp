@@ -67,6 +67,148 @@ void radix_sort_u64(std::vector<uint64_t> &a, int lo_bit)
     }
 }
 
+// Edge table from a caller's edge list (oriented triangles `tri`). Every
+// listed edge must be a side of each triangle it names, no two edges may
+// join the same two nodes, every side of every triangle must be on exactly
+// one listed edge, and the two triangles of an interior edge must lie on
+// opposite sides of it. The left cell of an interior edge is the one whose
+// counter-clockwise boundary runs from the lower to the higher node number
+// (the order the triangles are listed in does not matter), so the result
+// is the edge table the library would discover itself, in the caller's
+// edge numbering.
+bool edges_from_list(int64_t nn, int64_t nc, const std::vector<int32_t> &tri,
+                     const EdgeInput &in, int32_t max_tag,
+                     std::vector<int32_t> &e_left, std::vector<int8_t> &e_lk,
+                     std::vector<int32_t> &e_right,
+                     std::vector<int32_t> &e_tag,
+                     std::vector<int32_t> &side_edge, int64_t &nb,
+                     std::string &err)
+{
+    const int64_t ne = in.n;
+    if (ne < 0 || ne > INT32_MAX) {
+        err = "edge count out of range";
+        return false;
+    }
+    if (ne > 0 && (!in.nodes || !in.cells)) {
+        err = "null edge array";
+        return false;
+    }
+    e_left.assign(ne, -1);
+    e_lk.assign(ne, 0);
+    e_right.assign(ne, -1);
+    e_tag.assign(ne, 0);
+    side_edge.assign(3 * nc, -1);
+    nb = 0;
+    // local side of triangle c joining nodes p and q, or -1
+    auto side_of = [&](int64_t c, int32_t p, int32_t q) {
+        for (int k = 0; k < 3; ++k) {
+            const int32_t a = tri[3 * c + k], b = tri[3 * c + (k + 1) % 3];
+            if ((a == p && b == q) || (a == q && b == p)) return k;
+        }
+        return -1;
+    };
+    std::vector<int32_t> lo_count(nn + 1, 0);
+    for (int64_t e = 0; e < ne; ++e) {
+        const int32_t p = in.nodes[2 * e], q = in.nodes[2 * e + 1];
+        if (p < 0 || q < 0 || p >= nn || q >= nn || p == q) {
+            err = fmt("edge %lld has invalid nodes (%d,%d)", (long long)e, p, q);
+            return false;
+        }
+        int32_t cs[2] = {in.cells[2 * e], in.cells[2 * e + 1]};
+        if (cs[0] < 0 && cs[1] < 0) {
+            err = fmt("edge %lld names no triangle", (long long)e);
+            return false;
+        }
+        if (cs[0] == cs[1]) {
+            err = fmt("edge %lld names triangle %d twice", (long long)e, cs[0]);
+            return false;
+        }
+        int ks[2] = {-1, -1};
+        for (int j = 0; j < 2; ++j) {
+            const int32_t c = cs[j];
+            if (c < -1 || c >= nc) {
+                err = fmt("edge %lld names triangle %d out of range",
+                          (long long)e, c);
+                return false;
+            }
+            if (c < 0) continue;
+            ks[j] = side_of(c, p, q);
+            if (ks[j] < 0) {
+                err = fmt("edge %lld (%d,%d) is not a side of triangle %d",
+                          (long long)e, p, q, c);
+                return false;
+            }
+            int32_t &slot = side_edge[3 * int64_t(c) + ks[j]];
+            if (slot >= 0) {
+                err = fmt("side (%d,%d) of triangle %d is listed by edges %d "
+                          "and %lld", p, q, c, slot, (long long)e);
+                return false;
+            }
+            slot = int32_t(e);
+        }
+        const int32_t tag = in.tag ? in.tag[e] : 0;
+        const bool interior = cs[0] >= 0 && cs[1] >= 0;
+        if (interior ? tag != 0 : (tag < 0 || tag >= max_tag)) {
+            err = interior
+                      ? fmt("interior edge %lld carries tag %d (must be 0)",
+                            (long long)e, tag)
+                      : fmt("boundary edge %lld has tag %d outside [0,%d)",
+                            (long long)e, tag, max_tag);
+            return false;
+        }
+        // does side k of triangle c run from the lower to the higher node?
+        auto fwd = [&](int32_t c, int k) {
+            return tri[3 * int64_t(c) + k] < tri[3 * int64_t(c) + (k + 1) % 3];
+        };
+        if (interior) {
+            if (fwd(cs[0], ks[0]) == fwd(cs[1], ks[1])) {
+                err = fmt("triangles %d and %d overlap along edge %lld",
+                          cs[0], cs[1], (long long)e);
+                return false;
+            }
+            const int l = fwd(cs[0], ks[0]) ? 0 : 1;
+            e_left[e] = cs[l];
+            e_lk[e] = int8_t(ks[l]);
+            e_right[e] = cs[1 - l];
+        } else {
+            const int j = cs[0] >= 0 ? 0 : 1;
+            e_left[e] = cs[j];
+            e_lk[e] = int8_t(ks[j]);
+            e_tag[e] = tag;
+            ++nb;
+        }
+        ++lo_count[std::min(p, q) + 1];
+    }
+    for (int64_t c = 0; c < nc; ++c)
+        for (int k = 0; k < 3; ++k)
+            if (side_edge[3 * c + k] < 0) {
+                err = fmt("side %d of triangle %lld is on no listed edge", k,
+                          (long long)c);
+                return false;
+            }
+    // no two edges may join the same nodes (a third triangle on a side)
+    for (int64_t n = 0; n < nn; ++n) lo_count[n + 1] += lo_count[n];
+    std::vector<int32_t> hi(ne);
+    {
+        std::vector<int32_t> fill(lo_count.begin(), lo_count.end() - 1);
+        for (int64_t e = 0; e < ne; ++e) {
+            const int32_t p = in.nodes[2 * e], q = in.nodes[2 * e + 1];
+            hi[fill[std::min(p, q)]++] = std::max(p, q);
+        }
+    }
+    for (int64_t n = 0; n < nn; ++n) {
+        int32_t *b0 = hi.data() + lo_count[n], *b1 = hi.data() + lo_count[n + 1];
+        std::sort(b0, b1);
+        for (int32_t *x = b0; x + 1 < b1; ++x)
+            if (x[0] == x[1]) {
+                err = fmt("two edges join nodes %lld and %d", (long long)n,
+                          x[0]);
+                return false;
+            }
+    }
+    return true;
+}
+
 }  // namespace
 
 bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
@@ -74,7 +216,8 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
                       const int32_t *bnd_nodes, const int32_t *bnd_tag,
                       int32_t block_cells, bool reorder,
                       const uint8_t *group, int32_t wet_band,
-                      int32_t max_tag, BlockMesh &M, std::string &err)
+                      int32_t max_tag, BlockMesh &M, std::string &err,
+                      const EdgeInput *edges)
 {
     M = BlockMesh();
     if (nn < 3 || nc < 1) {
@@ -144,184 +287,197 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
         return false;
     }
 
-    // ---- unique edges: bucket the 3 nc sides by their lower node, then
-    //      sort each (short) bucket by (higher node, side)
-    std::vector<int64_t> start(nn + 1, 0);
-    {
-        std::vector<int32_t> cnt(nn, 0);
+    // ---- the edge table: left cell and its side, right cell (-1 on the
+    //      boundary), tag, and the edge of every cell side
+    std::vector<int32_t> e_left, e_right, e_tag, side_edge;
+    std::vector<int8_t> e_lk;
+    int64_t ne = 0, nb = 0;
+    if (edges) {
+        if (!edges_from_list(nn, nc, tri, *edges, max_tag, e_left, e_lk,
+                             e_right, e_tag, side_edge, nb, err))
+            return false;
+        ne = edges->n;
+    } else {
+        // ---- unique edges: bucket the 3 nc sides by their lower node, then
+        //      sort each (short) bucket by (higher node, side)
+        std::vector<int64_t> start(nn + 1, 0);
+        {
+            std::vector<int32_t> cnt(nn, 0);
 #pragma omp parallel for schedule(static)
-        for (int64_t s = 0; s < 3 * nc; ++s) {
-            const int64_t c = s / 3;
-            const int k = int(s % 3);
-            const int32_t p = tri[3 * c + k], q = tri[3 * c + (k + 1) % 3];
+            for (int64_t s = 0; s < 3 * nc; ++s) {
+                const int64_t c = s / 3;
+                const int k = int(s % 3);
+                const int32_t p = tri[3 * c + k], q = tri[3 * c + (k + 1) % 3];
 #pragma omp atomic
-            cnt[std::min(p, q)] += 1;
+                cnt[std::min(p, q)] += 1;
+            }
+            for (int64_t n = 0; n < nn; ++n) start[n + 1] = start[n] + cnt[n];
         }
-        for (int64_t n = 0; n < nn; ++n) start[n + 1] = start[n] + cnt[n];
-    }
-    std::vector<int32_t> bucket(3 * nc);
-    {
-        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        std::vector<int32_t> bucket(3 * nc);
+        {
+            std::vector<int64_t> fill(start.begin(), start.end() - 1);
 #pragma omp parallel for schedule(static)
-        for (int64_t s = 0; s < 3 * nc; ++s) {
-            const int64_t c = s / 3;
-            const int k = int(s % 3);
-            const int32_t p = tri[3 * c + k], q = tri[3 * c + (k + 1) % 3];
-            int64_t at;
+            for (int64_t s = 0; s < 3 * nc; ++s) {
+                const int64_t c = s / 3;
+                const int k = int(s % 3);
+                const int32_t p = tri[3 * c + k], q = tri[3 * c + (k + 1) % 3];
+                int64_t at;
 #pragma omp atomic capture
-            at = fill[std::min(p, q)]++;
-            bucket[at] = int32_t(s);
+                at = fill[std::min(p, q)]++;
+                bucket[at] = int32_t(s);
+            }
         }
-    }
-    auto hi_node = [&](int32_t s) {
-        const int64_t c = s / 3;
-        const int k = s % 3;
-        return std::max(tri[3 * c + k], tri[3 * c + (k + 1) % 3]);
-    };
-    auto fwd = [&](int32_t s) {   // side runs from lower to higher node
-        const int64_t c = s / 3;
-        const int k = s % 3;
-        return tri[3 * c + k] < tri[3 * c + (k + 1) % 3];
-    };
+        auto hi_node = [&](int32_t s) {
+            const int64_t c = s / 3;
+            const int k = s % 3;
+            return std::max(tri[3 * c + k], tri[3 * c + (k + 1) % 3]);
+        };
+        auto fwd = [&](int32_t s) {   // side runs from lower to higher node
+            const int64_t c = s / 3;
+            const int k = s % 3;
+            return tri[3 * c + k] < tri[3 * c + (k + 1) % 3];
+        };
 
-    // boundary segments bucketed by their lower node
-    std::vector<int64_t> sstart(nn + 1, 0);
-    std::vector<int32_t> sbucket(nbnd);
-    std::vector<char> sused(nbnd, 0);
-    for (int64_t s = 0; s < nbnd; ++s) {
-        const int32_t p = bnd_nodes[2 * s], q = bnd_nodes[2 * s + 1];
-        if (p < 0 || q < 0 || p >= nn || q >= nn || p == q) {
-            err = fmt("boundary segment %lld has invalid nodes", (long long)s);
-            return false;
-        }
-        if (bnd_tag[s] < 0 || bnd_tag[s] >= max_tag) {
-            err = fmt("boundary segment %lld has tag %d outside [0,%d)",
-                      (long long)s, bnd_tag[s], max_tag);
-            return false;
-        }
-        ++sstart[std::min(p, q) + 1];
-    }
-    for (int64_t n = 0; n < nn; ++n) sstart[n + 1] += sstart[n];
-    {
-        std::vector<int64_t> fill(sstart.begin(), sstart.end() - 1);
+        // boundary segments bucketed by their lower node
+        std::vector<int64_t> sstart(nn + 1, 0);
+        std::vector<int32_t> sbucket(nbnd);
+        std::vector<char> sused(nbnd, 0);
         for (int64_t s = 0; s < nbnd; ++s) {
             const int32_t p = bnd_nodes[2 * s], q = bnd_nodes[2 * s + 1];
-            sbucket[fill[std::min(p, q)]++] = int32_t(s);
+            if (p < 0 || q < 0 || p >= nn || q >= nn || p == q) {
+                err = fmt("boundary segment %lld has invalid nodes", (long long)s);
+                return false;
+            }
+            if (bnd_tag[s] < 0 || bnd_tag[s] >= max_tag) {
+                err = fmt("boundary segment %lld has tag %d outside [0,%d)",
+                          (long long)s, bnd_tag[s], max_tag);
+                return false;
+            }
+            ++sstart[std::min(p, q) + 1];
         }
-    }
+        for (int64_t n = 0; n < nn; ++n) sstart[n + 1] += sstart[n];
+        {
+            std::vector<int64_t> fill(sstart.begin(), sstart.end() - 1);
+            for (int64_t s = 0; s < nbnd; ++s) {
+                const int32_t p = bnd_nodes[2 * s], q = bnd_nodes[2 * s + 1];
+                sbucket[fill[std::min(p, q)]++] = int32_t(s);
+            }
+        }
 
-    // pass 1: sort each bucket, validate, count its unique edges
-    std::vector<int64_t> estart(nn + 1, 0);
-    int64_t bad_node = INT64_MAX;
+        // pass 1: sort each bucket, validate, count its unique edges
+        std::vector<int64_t> estart(nn + 1, 0);
+        int64_t bad_node = INT64_MAX;
 #pragma omp parallel for schedule(dynamic, 4096) reduction(min : bad_node)
-    for (int64_t a = 0; a < nn; ++a) {
-        int32_t *b0 = bucket.data() + start[a];
-        int32_t *b1 = bucket.data() + start[a + 1];
-        std::sort(b0, b1, [&](int32_t u, int32_t v) {
-            const int32_t bu = hi_node(u), bv = hi_node(v);
-            return bu != bv ? bu < bv : u < v;
-        });
-        int64_t ne_a = 0;
-        for (int32_t *i = b0; i < b1;) {
-            int32_t *j = i + 1;
-            while (j < b1 && hi_node(*j) == hi_node(*i)) ++j;
-            if (j - i > 2 || (j - i == 2 && fwd(i[0]) == fwd(i[1])))
-                bad_node = std::min(bad_node, a);
-            ++ne_a;
-            i = j;
-        }
-        estart[a + 1] = ne_a;
-    }
-    if (bad_node != INT64_MAX) {
-        const int64_t a = bad_node;
-        for (int64_t i = start[a]; i < start[a + 1];) {
-            int64_t j = i + 1;
-            while (j < start[a + 1] && hi_node(bucket[j]) == hi_node(bucket[i]))
-                ++j;
-            const int32_t b = hi_node(bucket[i]);
-            if (j - i > 2) {
-                err = fmt("edge (%lld,%d) is shared by more than two triangles",
-                          (long long)a, b);
-                return false;
+        for (int64_t a = 0; a < nn; ++a) {
+            int32_t *b0 = bucket.data() + start[a];
+            int32_t *b1 = bucket.data() + start[a + 1];
+            std::sort(b0, b1, [&](int32_t u, int32_t v) {
+                const int32_t bu = hi_node(u), bv = hi_node(v);
+                return bu != bv ? bu < bv : u < v;
+            });
+            int64_t ne_a = 0;
+            for (int32_t *i = b0; i < b1;) {
+                int32_t *j = i + 1;
+                while (j < b1 && hi_node(*j) == hi_node(*i)) ++j;
+                if (j - i > 2 || (j - i == 2 && fwd(i[0]) == fwd(i[1])))
+                    bad_node = std::min(bad_node, a);
+                ++ne_a;
+                i = j;
             }
-            if (j - i == 2 && fwd(bucket[i]) == fwd(bucket[i + 1])) {
-                err = fmt("triangles %d and %d overlap along edge (%lld,%d)",
-                          bucket[i] / 3, bucket[i + 1] / 3, (long long)a, b);
-                return false;
-            }
-            i = j;
+            estart[a + 1] = ne_a;
         }
-    }
-    for (int64_t a = 0; a < nn; ++a) estart[a + 1] += estart[a];
-    const int64_t ne = estart[nn];
-    if (ne > INT32_MAX) {
-        err = "mesh too large for 32-bit edge indices";
-        return false;
-    }
-
-    // pass 2: edge table in (lower node, higher node) order
-    std::vector<int32_t> e_left(ne), e_right(ne), e_tag(ne);
-    std::vector<int8_t> e_lk(ne);
-    std::vector<int32_t> side_edge(3 * nc);
-    int64_t nb = 0;
-#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : nb)
-    for (int64_t a = 0; a < nn; ++a) {
-        int64_t e = estart[a];
-        for (int64_t i = start[a]; i < start[a + 1]; ++e) {
-            int64_t j = i + 1;
-            while (j < start[a + 1] && hi_node(bucket[j]) == hi_node(bucket[i]))
-                ++j;
-            const int32_t b = hi_node(bucket[i]);
-            if (j - i == 2) {
-                const int32_t l = fwd(bucket[i]) ? bucket[i] : bucket[i + 1];
-                const int32_t r = fwd(bucket[i]) ? bucket[i + 1] : bucket[i];
-                e_left[e] = l / 3;
-                e_lk[e] = int8_t(l % 3);
-                e_right[e] = r / 3;
-                e_tag[e] = 0;
-                side_edge[l] = int32_t(e);
-                side_edge[r] = int32_t(e);
-            } else {
-                const int32_t l = bucket[i];
-                int32_t tag = 0;
-                for (int64_t k = sstart[a]; k < sstart[a + 1]; ++k) {
-                    const int32_t s = sbucket[k];
-                    if (std::max(bnd_nodes[2 * s], bnd_nodes[2 * s + 1]) == b) {
-                        sused[s] = 1;
-                        tag = bnd_tag[s];
-                        break;
-                    }
+        if (bad_node != INT64_MAX) {
+            const int64_t a = bad_node;
+            for (int64_t i = start[a]; i < start[a + 1];) {
+                int64_t j = i + 1;
+                while (j < start[a + 1] && hi_node(bucket[j]) == hi_node(bucket[i]))
+                    ++j;
+                const int32_t b = hi_node(bucket[i]);
+                if (j - i > 2) {
+                    err = fmt("edge (%lld,%d) is shared by more than two triangles",
+                              (long long)a, b);
+                    return false;
                 }
-                e_left[e] = l / 3;
-                e_lk[e] = int8_t(l % 3);
-                e_right[e] = -1;
-                e_tag[e] = tag;
-                side_edge[l] = int32_t(e);
-                ++nb;
+                if (j - i == 2 && fwd(bucket[i]) == fwd(bucket[i + 1])) {
+                    err = fmt("triangles %d and %d overlap along edge (%lld,%d)",
+                              bucket[i] / 3, bucket[i + 1] / 3, (long long)a, b);
+                    return false;
+                }
+                i = j;
             }
-            i = j;
         }
-    }
-    for (int64_t s = 0; s < nbnd; ++s)
-        if (!sused[s]) {
-            // either a duplicate of a used segment or not a boundary edge
-            const int32_t p = bnd_nodes[2 * s], q = bnd_nodes[2 * s + 1];
-            bool dup = false;
-            for (int64_t k = sstart[std::min(p, q)];
-                 k < sstart[std::min(p, q) + 1]; ++k) {
-                const int32_t t = sbucket[k];
-                if (t != s && sused[t] &&
-                    std::max(bnd_nodes[2 * t], bnd_nodes[2 * t + 1]) ==
-                        std::max(p, q))
-                    dup = true;
-            }
-            err = dup ? fmt("boundary segment (%d,%d) listed twice", p, q)
-                      : fmt("boundary segment (%d,%d) is not a boundary edge "
-                            "of the mesh", p, q);
+        for (int64_t a = 0; a < nn; ++a) estart[a + 1] += estart[a];
+        ne = estart[nn];
+        if (ne > INT32_MAX) {
+            err = "mesh too large for 32-bit edge indices";
             return false;
         }
-    std::vector<int64_t>().swap(start);
-    std::vector<int32_t>().swap(bucket);
+
+        // pass 2: edge table in (lower node, higher node) order
+        e_left.resize(ne);
+        e_right.resize(ne);
+        e_tag.resize(ne);
+        e_lk.resize(ne);
+        side_edge.resize(3 * nc);
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : nb)
+        for (int64_t a = 0; a < nn; ++a) {
+            int64_t e = estart[a];
+            for (int64_t i = start[a]; i < start[a + 1]; ++e) {
+                int64_t j = i + 1;
+                while (j < start[a + 1] && hi_node(bucket[j]) == hi_node(bucket[i]))
+                    ++j;
+                const int32_t b = hi_node(bucket[i]);
+                if (j - i == 2) {
+                    const int32_t l = fwd(bucket[i]) ? bucket[i] : bucket[i + 1];
+                    const int32_t r = fwd(bucket[i]) ? bucket[i + 1] : bucket[i];
+                    e_left[e] = l / 3;
+                    e_lk[e] = int8_t(l % 3);
+                    e_right[e] = r / 3;
+                    e_tag[e] = 0;
+                    side_edge[l] = int32_t(e);
+                    side_edge[r] = int32_t(e);
+                } else {
+                    const int32_t l = bucket[i];
+                    int32_t tag = 0;
+                    for (int64_t k = sstart[a]; k < sstart[a + 1]; ++k) {
+                        const int32_t s = sbucket[k];
+                        if (std::max(bnd_nodes[2 * s], bnd_nodes[2 * s + 1]) == b) {
+                            sused[s] = 1;
+                            tag = bnd_tag[s];
+                            break;
+                        }
+                    }
+                    e_left[e] = l / 3;
+                    e_lk[e] = int8_t(l % 3);
+                    e_right[e] = -1;
+                    e_tag[e] = tag;
+                    side_edge[l] = int32_t(e);
+                    ++nb;
+                }
+                i = j;
+            }
+        }
+        for (int64_t s = 0; s < nbnd; ++s)
+            if (!sused[s]) {
+                // either a duplicate of a used segment or not a boundary edge
+                const int32_t p = bnd_nodes[2 * s], q = bnd_nodes[2 * s + 1];
+                bool dup = false;
+                for (int64_t k = sstart[std::min(p, q)];
+                     k < sstart[std::min(p, q) + 1]; ++k) {
+                    const int32_t t = sbucket[k];
+                    if (t != s && sused[t] &&
+                        std::max(bnd_nodes[2 * t], bnd_nodes[2 * t + 1]) ==
+                            std::max(p, q))
+                        dup = true;
+                }
+                err = dup ? fmt("boundary segment (%d,%d) listed twice", p, q)
+                          : fmt("boundary segment (%d,%d) is not a boundary edge "
+                                "of the mesh", p, q);
+                return false;
+            }
+        std::vector<int64_t>().swap(start);
+        std::vector<int32_t>().swap(bucket);
+    }
 
     // edge geometry from the left cell's counter-clockwise traversal p -> q:
     // L = |q - p|, outward normal (dy, -dx) / L
@@ -338,9 +494,26 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
         enx[e] = dy / L;
         eny[e] = -dx / L;
     }
+    // boundary length per tag, summed in (lower node, higher node) order
+    // whatever the edge numbering, so the inflow per unit length rounds the
+    // same for a discovered and a listed edge table
     M.tag_length.assign(max_tag, 0.0);
-    for (int64_t e = 0; e < ne; ++e)
-        if (e_right[e] < 0) M.tag_length[e_tag[e]] += elen[e];
+    {
+        std::vector<std::pair<uint64_t, int32_t>> bnd;
+        bnd.reserve(size_t(nb));
+        for (int64_t e = 0; e < ne; ++e)
+            if (e_right[e] < 0) {
+                const int64_t c = e_left[e];
+                const int k = e_lk[e];
+                const uint32_t p = uint32_t(tri[3 * c + k]);
+                const uint32_t q = uint32_t(tri[3 * c + (k + 1) % 3]);
+                bnd.emplace_back(uint64_t(std::min(p, q)) << 32 |
+                                     uint64_t(std::max(p, q)),
+                                 int32_t(e));
+            }
+        std::sort(bnd.begin(), bnd.end());
+        for (const auto &b : bnd) M.tag_length[e_tag[b.second]] += elen[b.second];
+    }
 
     // ---- internal cell order: Hilbert curve through the centroids, on a
     //      square lattice covering the bounding box (ties keep user order)

@@ -61,7 +61,21 @@ struct BlockMesh {
 // Neighbour blocks kept per block for skipping dormant blocks.
 constexpr int kNbrSlots = 64;
 
+// Edges given by the caller instead of discovered from the triangles:
+// n edges, nodes[2e], nodes[2e+1] (either order), cells[2e], cells[2e+1]
+// (the one or two triangles on the edge, in either slot; -1 in the other
+// slot on the boundary), tag[e] (boundary edges, in [0, max_tag); 0 on
+// interior edges; tag null = all 0).
+struct EdgeInput {
+    int64_t n = 0;
+    const int32_t *nodes = nullptr;
+    const int32_t *cells = nullptr;
+    const int32_t *tag = nullptr;
+};
+
 // Builds the block mesh. Returns false and sets err on an invalid mesh.
+// With edges non-null, the edge table and the boundary tags are taken from
+// it (validated against the triangles) and the segments are not used.
 // With reorder, cells follow a Hilbert curve through their centroids; with
 // group (one value per cell, or null) too, cells are ordered by group first
 // and along the curve within a group. With wet_band >= 0, group is instead
@@ -72,6 +86,7 @@ bool build_block_mesh(int64_t n_nodes, const double *xy, int64_t n_cells,
                       const int32_t *bnd_nodes, const int32_t *bnd_tag,
                       int32_t block_cells, bool reorder,
                       const uint8_t *group, int32_t wet_band,
-                      int32_t max_tag, BlockMesh &out, std::string &err);
+                      int32_t max_tag, BlockMesh &out, std::string &err,
+                      const EdgeInput *edges = nullptr);
 
 }  // namespace swe

@@ -108,6 +108,9 @@ def load():
     L.swe_set_mesh.restype = st
     L.swe_set_mesh.argtypes = [_p, C.c_int64, _pd, C.c_int64, _pi32,
                                C.c_int64, _pi32, _pi32]
+    L.swe_set_mesh_edges.restype = st
+    L.swe_set_mesh_edges.argtypes = [_p, C.c_int64, _pd, C.c_int64, _pi32,
+                                     C.c_int64, _pi32, _pi32, _pi32]
     L.swe_set_cell_groups.restype = st
     L.swe_set_cell_groups.argtypes = [_p, C.c_int64, C.POINTER(C.c_uint8)]
     L.swe_set_wet_cells.restype = st
@@ -115,6 +118,8 @@ def load():
                                     C.c_int32]
     L.swe_mesh_info.restype = st
     L.swe_mesh_info.argtypes = [_p, C.POINTER(swe_mesh_stats)]
+    L.swe_mesh_digest.restype = st
+    L.swe_mesh_digest.argtypes = [_p, C.POINTER(C.c_uint64)]
     L.swe_get_cell_order.restype = st
     L.swe_get_cell_order.argtypes = [_p, _pi32]
     L.swe_get_geometry.restype = st
@@ -271,6 +276,27 @@ def swe_set_mesh(ctx, xy, tri, bnd=None, bnd_tag=None):
         bnd_tag.ctypes.data_as(_pi32)))
 
 
+def swe_set_mesh_edges(ctx, xy, tri, edge_nodes, edge_cells, edge_tag=None):
+    """Mesh with its edges given: edge_nodes (n, 2), edge_cells (n, 2) with
+    -1 in one slot on the boundary, edge_tag (n,) or None (all 0)."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+    en = np.ascontiguousarray(edge_nodes, dtype=np.int32).reshape(-1, 2)
+    ec = np.ascontiguousarray(edge_cells, dtype=np.int32).reshape(-1, 2)
+    if ec.shape[0] != en.shape[0]:
+        raise ValueError("edge_cells must have one row per edge")
+    tag_p = None
+    if edge_tag is not None:
+        et = np.ascontiguousarray(edge_tag, dtype=np.int32).reshape(-1)
+        if et.size != en.shape[0]:
+            raise ValueError("edge_tag must have one tag per edge")
+        tag_p = et.ctypes.data_as(_pi32)
+    _check(ctx, load().swe_set_mesh_edges(
+        ctx, xy.shape[0], xy.ctypes.data_as(_pd), tri.shape[0],
+        tri.ctypes.data_as(_pi32), en.shape[0], en.ctypes.data_as(_pi32),
+        ec.ctypes.data_as(_pi32), tag_p))
+
+
 def swe_set_cell_groups(ctx, group):
     """Cell groups (uint8, user order) for the next swe_set_mesh; None
     clears them."""
@@ -294,6 +320,12 @@ def swe_mesh_info(ctx):
     s = swe_mesh_stats()
     _check(ctx, load().swe_mesh_info(ctx, C.byref(s)))
     return {k: getattr(s, k) for k, _ in swe_mesh_stats._fields_}
+
+
+def swe_mesh_digest(ctx):
+    d = C.c_uint64()
+    _check(ctx, load().swe_mesh_digest(ctx, C.byref(d)))
+    return d.value
 
 
 def swe_get_cell_order(ctx):
@@ -535,11 +567,13 @@ class Solver:
     lets the far dry blocks fall dormant, at the price of longer records
     in the seam blocks: it pays on large launches (throughput-bound) and not
     on small ones, whose step waits for their slowest block; wet_band=None
-    takes 2 from a million cells on, else 0."""
+    takes 2 from a million cells on, else 0. With edges = (edge_nodes,
+    edge_cells, edge_tag) the mesh is given with its edges
+    (swe_set_mesh_edges) instead of boundary segments."""
 
     def __init__(self, case, device=0, workspace="torch", stream="torch",
                  block_cells=256, reorder=True, params=None, group_wet=True,
-                 wet_band=None):
+                 wet_band=None, edges=None):
         self.ctx = swe_create(device)
         self._ws = None
         self.device = device
@@ -556,7 +590,11 @@ class Solver:
                 if wet_band is None:
                     wet_band = 2 if case.n_cells >= 1_000_000 else 0
                 swe_set_wet_cells(self.ctx, case.h > p.h_dry, wet_band)
-            swe_set_mesh(self.ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
+            if edges is None:
+                swe_set_mesh(self.ctx, case.xy, case.tri, case.bnd,
+                             case.bnd_tag)
+            else:
+                swe_set_mesh_edges(self.ctx, case.xy, case.tri, *edges)
             for tag, (kind, value) in case.bc.items():
                 swe_set_bc(self.ctx, tag, kind, value)
             swe_set_bathymetry(self.ctx, case.z)

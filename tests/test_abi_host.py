@@ -289,3 +289,113 @@ def test_ensemble_assembly_on_the_host():
     finally:
         S.swe_destroy(ca)
         S.swe_destroy(cb)
+
+
+# ------------------------------------------------- mesh given with its edges
+
+@pytest.mark.parametrize("case", [
+    W.dam_break_canal(nx=30, ny=7, lx=30.0, ly=7.0),
+    W.river(n_target=30_000, workers=1)])
+@pytest.mark.parametrize("band", [None, 2])
+def test_listed_edges_give_the_discovered_mesh(ctx, case, band):
+    """The edge-to-cell connectivity and boundary tags given as an edge list
+    (shuffled, slots swapped) yield the same internal mesh, bit for bit, as
+    the triangles with tagged boundary segments (sec. 3.1 mesh)."""
+    if band is not None:
+        S.swe_set_wet_cells(ctx, case.h > case.h_dry, band)
+    S.swe_set_mesh(ctx, case.xy, case.tri, case.bnd, case.bnd_tag)
+    ref = S.swe_mesh_digest(ctx), S.swe_mesh_info(ctx)
+    for seed in (1, 2):
+        if band is not None:
+            S.swe_set_wet_cells(ctx, case.h > case.h_dry, band)
+        S.swe_set_mesh_edges(ctx, case.xy, case.tri,
+                             *W.edge_list(case, seed=seed))
+        assert (S.swe_mesh_digest(ctx), S.swe_mesh_info(ctx)) == ref
+    # a tag differs: the digest sees it
+    en, ec, et = W.edge_list(case, seed=3)
+    et = et.copy()
+    et[np.flatnonzero(et)[0]] += 1
+    S.swe_set_mesh_edges(ctx, case.xy, case.tri, en, ec, et)
+    assert S.swe_mesh_digest(ctx) != ref[0]
+
+
+def _two_squares():
+    """Two unit squares side by side, four triangles."""
+    xy = np.array([[0, 0], [1, 0], [2, 0], [0, 1], [1, 1], [2, 1]], float)
+    tri = np.array([[0, 1, 4], [0, 4, 3], [1, 2, 5], [1, 5, 4]], np.int32)
+    case = W.Case(name="two-squares", xy=xy, tri=tri,
+                  bnd=np.zeros((0, 2), np.int32),
+                  bnd_tag=np.zeros(0, np.int32), bc={}, z=np.zeros(4),
+                  manning=np.zeros(4), h=np.ones(4), hu=np.zeros(4),
+                  hv=np.zeros(4))
+    return case
+
+
+def test_edge_list_errors(ctx):
+    case = _two_squares()
+    en, ec, et = W.edge_list(case, seed=0)
+    interior = np.flatnonzero((ec >= 0).all(axis=1))
+    boundary = np.flatnonzero((ec < 0).any(axis=1))
+    S.swe_set_mesh_edges(ctx, case.xy, case.tri, en, ec, et)   # valid
+
+    def rejected(en2, ec2, et2, words):
+        with pytest.raises(S.SweError) as e:
+            S.swe_set_mesh_edges(ctx, case.xy, case.tri, en2, ec2, et2)
+        assert e.value.status == S.SWE_EMESH, str(e.value)
+        assert words in str(e.value), str(e.value)
+
+    # an edge naming a triangle it does not bound
+    ec2 = ec.copy()
+    k = interior[0]
+    others = [c for c in range(4) if c not in ec[k]]
+    ec2[k, 0] = others[0]
+    rejected(en, ec2, et, "is not a side of triangle")
+    # a side left out
+    keep = np.arange(len(en)) != boundary[0]
+    rejected(en[keep], ec[keep], et[keep], "is on no listed edge")
+    # the same side listed twice
+    rejected(np.vstack([en, en[:1]]), np.vstack([ec, ec[:1]]),
+             np.append(et, et[:1]), "is listed by edges")
+    # a nonzero tag on an interior edge, a tag out of range
+    et2 = et.copy()
+    et2[interior[0]] = 3
+    rejected(en, ec, et2, "interior edge")
+    et2 = et.copy()
+    et2[boundary[0]] = 5000
+    rejected(en, ec, et2, "outside")
+    # a triangle index out of range, no triangle at all, one named twice
+    ec2 = ec.copy()
+    ec2[boundary[0]] = [7, -1]
+    rejected(en, ec2, et, "out of range")
+    ec2 = ec.copy()
+    ec2[boundary[0]] = [-1, -1]
+    rejected(en, ec2, et, "names no triangle")
+    ec2 = ec.copy()
+    ec2[interior[0]] = [ec[interior[0], 0]] * 2
+    rejected(en, ec2, et, "twice")
+    # nodes out of range
+    en2 = en.copy()
+    en2[0] = [0, 99]
+    rejected(en2, ec, et, "invalid nodes")
+
+
+def test_edge_list_overlap_and_third_triangle(ctx):
+    """Two triangles on the same side of an edge, and a third triangle on a
+    side (non-manifold), are rejected."""
+    xy = np.array([[0, 0], [1, 0], [0.5, 1], [0.5, 2], [0.5, -1]], float)
+    # triangles 0 and 1 both lie above edge (0,1): they overlap
+    tri = np.array([[0, 1, 2], [0, 1, 3]], np.int32)
+    en = np.array([[0, 1], [1, 2], [2, 0], [1, 3], [3, 0]], np.int32)
+    ec = np.array([[0, 1], [0, -1], [0, -1], [1, -1], [1, -1]], np.int32)
+    with pytest.raises(S.SweError) as e:
+        S.swe_set_mesh_edges(ctx, xy, tri, en, ec, None)
+    assert e.value.status == S.SWE_EMESH and "overlap" in str(e.value)
+    # three triangles on edge (0,1), listed as two edges with the same nodes
+    tri = np.array([[0, 1, 2], [1, 0, 4], [0, 1, 3]], np.int32)
+    en = np.array([[0, 1], [0, 1], [1, 2], [2, 0], [0, 4], [4, 1], [1, 3],
+                   [3, 0]], np.int32)
+    ec = np.array([[0, 1], [2, -1], [0, -1], [0, -1], [1, -1], [1, -1],
+                   [2, -1], [2, -1]], np.int32)
+    with pytest.raises(S.SweError) as e:
+        S.swe_set_mesh_edges(ctx, xy, tri, en, ec, None)
+    assert e.value.status == S.SWE_EMESH and "join" in str(e.value)

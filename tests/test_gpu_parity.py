@@ -486,3 +486,85 @@ def test_recorded_time_steps_replay_bitwise():
     c = solver(p)
     got = S.swe_advance_dt(c.ctx, 40, dts, record=True)
     assert np.array_equal(got, dts)
+
+
+def test_listed_edges_run_bitwise_like_discovered_edges():
+    """A mesh given with its edge list (shuffled edges, swapped slots, tags
+    per edge) runs bit for bit like the same mesh given as triangles with
+    tagged boundary segments: river with inflow, fixed stage and wet/dry."""
+    case = W.river(n_target=120_000, workers=1)
+    say(f"[edges] {case.name} cells={case.n_cells}")
+    a = solver(case)
+    b = solver(case, edges=W.edge_list(case, seed=9))
+    for s in (a, b):
+        s.advance(80)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    assert a.time() == b.time()
+    o = O.Oracle(case)
+    o.run(80)
+    for x, y in zip(b.state(), o.state()):
+        assert rel_linf(x, y) <= FULL_RUN
+
+
+def test_deferred_numeric_error_surfaces_in_get_state():
+    """An asynchronous advance (t_end infinite, no time asked) that hits an
+    unbounded time step returns OK; the next synchronising call reports
+    it."""
+    from paper_2010_14416_amd import swe as S
+    case = W.dam_break_canal(nx=10, ny=2, lx=10.0, ly=2.0, h_left=0.0,
+                             h_right=0.0)
+    s = solver(case)
+    s.advance(3)
+    with pytest.raises(S.SweError) as e:
+        s.state()
+    assert e.value.status == S.SWE_ENUMERIC
+    s2 = solver(case)
+    s2.advance(2)
+    with pytest.raises(S.SweError) as e:
+        s2.diagnostics()
+    assert e.value.status == S.SWE_ENUMERIC
+
+
+def test_last_time_step_after_landing_on_t_end():
+    """The empty steps launched after t_end inside a polling batch leave the
+    last time step (the final, shortened one) and the step count as the
+    oracle reports them."""
+    from paper_2010_14416_amd import swe as S
+    case = W.dam_break_canal()
+    for every in (1, 5, 64):
+        s = solver(case, params={"check_every": every})
+        n, t = s.advance(10**6, 2.5)
+        o = O.Oracle(case)
+        n2, t2 = o.run(10**6, 2.5)
+        tg, dtg, kg = S.swe_get_time(s.ctx)
+        ck = o.clock()
+        assert t == tg == t2 == 2.5 and n == n2 == kg
+        assert dtg == ck["last_dt"] and dtg > 0.0, (every, dtg, ck)
+
+
+def test_device_bed_change_wakes_dormant_blocks():
+    """A bed given as device memory re-arms every block as a host bed does:
+    lowering the bed under a dry reach held by a fixed stage below its old
+    bed starts inflow there, also in blocks that had fallen dormant."""
+    import torch
+    case = W.bumps_canal(nx=120, ny=40, lx=30.0, ly=10.0, x_dam=6.0)
+    case.bc = dict(case.bc)
+    case.bc[2] = (W.BC_FIXED_STAGE, -0.5)       # east side, below the bed
+    a = solver(case)
+    b = solver(case, params={"store_all": 1})
+    for s in (a, b):
+        s.advance(100)
+    x = case.centroids()[:, 0]
+    z2 = case.z.copy()
+    z2[x > 24.0] = -1.0
+    zt = torch.tensor(z2, dtype=torch.float64, device="cuda")
+    m0 = a.diagnostics()[0]
+    for s in (a, b):
+        from paper_2010_14416_amd import swe as S
+        S.swe_set_bathymetry(s.ctx, zt)
+        s.advance(60)
+    for p, q in zip(a.state(), b.state()):
+        assert np.array_equal(p, q)
+    h = a.state()[0]
+    assert a.diagnostics()[0] > m0 and np.any(h[x > 29.0] > 0.1)

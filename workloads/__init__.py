@@ -127,6 +127,55 @@ def canal_mesh(nx: int, ny: int, lx: float, ly: float, x0: float = 0.0,
     return xy, tri, bnd, bnd_tag
 
 
+def edge_list(case: "Case", seed: int = 0):
+    """The case's mesh as an edge list: every pair of nodes that is a side of
+    a triangle, once, with the one or two triangles on it and the boundary
+    tag of a boundary edge (from ``bnd``/``bnd_tag``; 0 if unlisted and on
+    interior edges). Topology only. Edges come in a seeded random order, and
+    each edge's two node slots and two cell slots are swapped at random
+    (independently), so a consumer cannot rely on any ordering.
+
+    Returns ``edge_nodes (n, 2), edge_cells (n, 2) (-1 in one slot on the
+    boundary), edge_tag (n,)``, all int32.
+    """
+    rng = np.random.default_rng(seed)
+    tri = np.asarray(case.tri, dtype=np.int64)
+    nc = tri.shape[0]
+    p = tri.ravel()
+    q = np.roll(tri, -1, axis=1).ravel()
+    lo, hi = np.minimum(p, q), np.maximum(p, q)
+    key = lo * (case.n_nodes + 1) + hi
+    cell = np.repeat(np.arange(nc), 3)
+    order = np.argsort(key, kind="stable")
+    key, cell, lo, hi = key[order], cell[order], lo[order], hi[order]
+    first = np.ones(key.size, bool)
+    first[1:] = key[1:] != key[:-1]
+    starts = np.flatnonzero(first)
+    counts = np.diff(np.append(starts, key.size))
+    if np.any(counts > 2):
+        raise ValueError("a side is shared by more than two triangles")
+    n = starts.size
+    nodes = np.stack([lo[starts], hi[starts]], axis=1)
+    cells = np.full((n, 2), -1, np.int64)
+    cells[:, 0] = cell[starts]
+    two = counts == 2
+    cells[two, 1] = cell[starts[two] + 1]
+    tags = np.zeros(n, np.int64)
+    if len(case.bnd):
+        b = np.asarray(case.bnd, dtype=np.int64)
+        bkey = b.min(axis=1) * (case.n_nodes + 1) + b.max(axis=1)
+        at = np.searchsorted(key[starts], bkey)
+        tags[at] = case.bnd_tag
+    perm = rng.permutation(n)
+    nodes, cells, tags = nodes[perm], cells[perm], tags[perm]
+    swap_n = rng.random(n) < 0.5
+    nodes[swap_n] = nodes[swap_n][:, ::-1]
+    swap_c = rng.random(n) < 0.5
+    cells[swap_c] = cells[swap_c][:, ::-1]
+    return (nodes.astype(np.int32), cells.astype(np.int32),
+            tags.astype(np.int32))
+
+
 def _zeros(n):
     return np.zeros(n, dtype=np.float64)
 
