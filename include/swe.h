@@ -273,6 +273,25 @@ swe_status swe_advance(swe_ctx *ctx, int64_t max_steps, double t_end,
 swe_status swe_advance_dt(swe_ctx *ctx, int64_t n, const double *dt,
                           double *dt_out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): swe_advance_dt with the
+ * same arguments and results, bit for bit, that allocates nothing. The
+ * recorded time steps are staged in a fixed device array of the library
+ * (SWE_NOALLOC_MAX_STEPS doubles, 128 KiB, one per GPU, held until the
+ * process ends) instead of a buffer the context allocates. Limits and
+ * errors, beyond those of swe_advance_dt:
+ *  - with dt_out non-NULL, n > SWE_NOALLOC_MAX_STEPS returns SWE_EINVAL
+ *    (split the run into several calls);
+ *  - the context's device workspace must already exist (bound with
+ *    swe_bind_workspace, or allocated by an earlier call such as
+ *    swe_advance of 0 steps), else SWE_ENOTREADY.
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (contexts on different streams or threads) race on it. Synchronises the
+ * stream, as swe_advance_dt does. */
+#define SWE_NOALLOC_MAX_STEPS 16384
+swe_status swe_advance_dt_noalloc(swe_ctx *ctx, int64_t n, const double *dt,
+                                  double *dt_out);
+
 /* Discrete adjoint of a gauge misfit, for inverse analysis (calibrating
  * friction and bed against observed depths). From the current state, runs
  * `steps` ordinary steps (time steps recorded), evaluates

@@ -27,6 +27,7 @@ HIP_FLAGS = [
     "-ffp-contract=off",
     # no packed FP32 instructions (the step is FP64 throughout)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    f"-I{os.path.join(ROOT, 'include')}",
 ]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=off",
               "-fopenmp",
@@ -43,7 +44,7 @@ def build(verbose: bool = True) -> str:
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src in ["swe_kernels.hip", "swe_adjoint.hip"]:
+    for src in ["swe_kernels.hip", "swe_adjoint.hip", "swe_noalloc.hip"]:
         obj = os.path.join(BUILD, src + ".o")
         _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

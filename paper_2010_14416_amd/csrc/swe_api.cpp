@@ -939,6 +939,37 @@ swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
     return SWE_OK;
 }
 
+swe_status ctx_advance_dt_check(swe_ctx *c, int64_t n, const double *dt)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    if (n < 0) return fail(c, SWE_EINVAL, "negative step count");
+    if (dt)
+        for (int64_t k = 0; k < n; ++k)
+            if (!(dt[k] >= 0.0) || !std::isfinite(dt[k]))
+                return fail(c, SWE_EINVAL,
+                            "time step " + std::to_string(k) +
+                                " must be finite and >= 0");
+    return SWE_OK;
+}
+
+swe_status ctx_advance_dt(swe_ctx *c, int64_t n, const double *dt,
+                          double *dt_out, double *log)
+{
+    swe_status st;
+    if (!c->t_known) {
+        Clock ck;
+        if ((st = read_clock(c, &ck))) return st;
+    }
+    StepArgs a = ctx_step_args(c, INFINITY);
+    if ((st = ctx_enqueue(c, a, n, dt, dt_out ? log : nullptr))) return st;
+    if (dt_out)
+        HIPCHK(c, hipMemcpyAsync(dt_out, log, size_t(n) * 8,
+                                 hipMemcpyDeviceToHost, c->stream));
+    Clock ck;
+    return read_clock(c, &ck);
+}
+
 }  // namespace swe
 
 extern "C" {
@@ -984,33 +1015,15 @@ swe_status swe_advance(swe_ctx *c, int64_t max_steps, double t_end,
 swe_status swe_advance_dt(swe_ctx *c, int64_t n, const double *dt,
                           double *dt_out)
 {
-    swe_status st = require_mesh(c);
-    if (st != SWE_OK) return st;
-    if (n < 0) return fail(c, SWE_EINVAL, "negative step count");
-    if (n == 0) return SWE_OK;
-    if (dt)
-        for (int64_t k = 0; k < n; ++k)
-            if (!(dt[k] >= 0.0) || !std::isfinite(dt[k]))
-                return fail(c, SWE_EINVAL,
-                            "time step " + std::to_string(k) +
-                                " must be finite and >= 0");
+    swe_status st = swe::ctx_advance_dt_check(c, n, dt);
+    if (st != SWE_OK || n == 0) return st;
     if ((st = prepare(c))) return st;
-    if (!c->t_known) {
-        Clock ck;
-        if ((st = read_clock(c, &ck))) return st;
-    }
     double *log = nullptr;
     if (dt_out) {
         if ((st = swe::ctx_dt_buffer(c, n))) return st;
         log = c->dt_dev;
     }
-    swe::StepArgs a = swe::ctx_step_args(c, INFINITY);
-    if ((st = swe::ctx_enqueue(c, a, n, dt, log))) return st;
-    if (dt_out)
-        HIPCHK(c, hipMemcpyAsync(dt_out, log, size_t(n) * 8,
-                                 hipMemcpyDeviceToHost, c->stream));
-    Clock ck;
-    return read_clock(c, &ck);
+    return swe::ctx_advance_dt(c, n, dt, dt_out, log);
 }
 
 swe_status swe_get_diagnostics(swe_ctx *c, double *mass, double *ledger,

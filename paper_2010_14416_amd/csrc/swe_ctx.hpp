@@ -99,6 +99,13 @@ swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
 // context's ping-pong buffers, with time step dt (monitors not updated).
 swe_status ctx_step_between(swe_ctx *c, const double *const in[3],
                             double *const out[3], double dt);
+// Argument checks of a frozen-schedule advance (no device use).
+swe_status ctx_advance_dt_check(swe_ctx *c, int64_t n, const double *dt);
+// n steps with the host time steps dt (or the CFL time steps when dt is
+// null) on a prepared context; with dt_out, the time steps taken go through
+// the device buffer `log` (n values) to the host array dt_out. Synchronises.
+swe_status ctx_advance_dt(swe_ctx *c, int64_t n, const double *dt,
+                          double *dt_out, double *log);
 // Device buffer of at least n time steps in c->dt_dev.
 swe_status ctx_dt_buffer(swe_ctx *c, int64_t n);
 

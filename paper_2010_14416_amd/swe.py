@@ -142,6 +142,8 @@ def load():
     L.swe_advance.argtypes = [_p, C.c_int64, C.c_double, _pi64, _pd]
     L.swe_advance_dt.restype = st
     L.swe_advance_dt.argtypes = [_p, C.c_int64, _pd, _pd]
+    L.swe_advance_dt_noalloc.restype = st
+    L.swe_advance_dt_noalloc.argtypes = [_p, C.c_int64, _pd, _pd]
     L.swe_adjoint_gauges.restype = st
     L.swe_adjoint_gauges.argtypes = [_p, C.c_int64, C.c_int32, _pi32, _pd,
                                      C.c_int32, _pd, _pd, _pd]
@@ -423,6 +425,20 @@ def swe_advance_dt(ctx, n, dt=None, record=False):
         raise ValueError("need one time step per step")
     out = np.empty(n) if record else None
     _check(ctx, load().swe_advance_dt(
+        ctx, int(n), None if d is None else d.ctypes.data_as(_pd),
+        None if out is None else out.ctypes.data_as(_pd)))
+    return out
+
+
+def swe_advance_dt_noalloc(ctx, n, dt=None, record=False):
+    """swe_advance_dt that allocates no device memory (the context's
+    workspace must exist already; at most SWE_NOALLOC_MAX_STEPS recorded
+    time steps per call)."""
+    d = None if dt is None else np.ascontiguousarray(dt, dtype=np.float64)
+    if d is not None and d.size != n:
+        raise ValueError("need one time step per step")
+    out = np.empty(n) if record else None
+    _check(ctx, load().swe_advance_dt_noalloc(
         ctx, int(n), None if d is None else d.ctypes.data_as(_pd),
         None if out is None else out.ctypes.data_as(_pd)))
     return out
