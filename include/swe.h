@@ -95,7 +95,14 @@ typedef struct {
                               for the two previous steps skips its store,
                               since the output buffer already holds the same
                               values (0). Same results; a tuning switch      */
-    int32_t reserved;      /* must be 0                                       */
+    int32_t graph_steps;   /* 0: one kernel launch per step (default);
+                              K > 0, a multiple of 6 (at most 4096): runs of
+                              K steps are captured once in a HIP graph and
+                              replayed (swe_advance; the ensemble's
+                              swe_ens_advance likewise). Same results, bit
+                              for bit; fewer launch overheads on small
+                              meshes. A changed parameter, end time, stream
+                              or step phase triggers a new capture          */
 } swe_params;
 
 typedef struct {

@@ -49,7 +49,7 @@ def build(verbose: bool = True) -> str:
         _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in ["swe_mesh.cpp", "swe_api.cpp", "swe_ensemble.cpp",
-                "swe_adjoint.cpp"]:
+                "swe_adjoint.cpp", "swe_graph.cpp"]:
         obj = os.path.join(BUILD, src + ".o")
         _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

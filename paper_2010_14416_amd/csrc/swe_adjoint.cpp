@@ -264,7 +264,7 @@ extern "C" swe_status swe_adjoint_gauges(swe_ctx *c, int64_t steps,
     ADJCHK(c, hipMemcpyAsync(c->d.ledger, ledger_copy, nb * 8,
                              hipMemcpyDeviceToDevice, c->stream));
     ADJCHK(c, swe::launch_clock_set(c->d.clock, t_final, steps_final,
-                                    c->stream));
+                                    c->step_index, c->stream));
     ADJCHK(c, hipStreamSynchronize(c->stream));
     c->t_host = t_final;
     c->step_host = steps_final;

@@ -225,6 +225,7 @@ swe_status prepare(swe_ctx *c)
     }
     if (c->clock_dirty) {
         HIPCHK(c, swe::launch_clock_set(d.clock, c->t_host, c->step_host,
+                                        c->step_index,
                                         c->stream));
         c->clock_dirty = false;
         c->dt_valid = false;
@@ -367,7 +368,7 @@ swe_status swe_default_params(swe_params *p)
     p->load_schedule = 0;
     p->monitors = 0;
     p->store_all = 0;
-    p->reserved = 0;
+    p->graph_steps = 0;
     return SWE_OK;
 }
 
@@ -441,7 +442,9 @@ swe_status swe_set_params(swe_ctx *c, const swe_params *p)
         return fail(c, SWE_EINVAL, "monitors must be 0 or 1");
     if (p->store_all != 0 && p->store_all != 1)
         return fail(c, SWE_EINVAL, "store_all must be 0 or 1");
-    if (p->reserved != 0) return fail(c, SWE_EINVAL, "reserved must be 0");
+    if (p->graph_steps < 0 || p->graph_steps > 4096 || p->graph_steps % 6)
+        return fail(c, SWE_EINVAL,
+                    "graph_steps must be 0 or a multiple of 6 up to 4096");
     const bool g_changed = p->g != c->params.g;
     const bool dt_changed = g_changed || p->h_dry != c->params.h_dry;
     if (p->monitors && !c->params.monitors) c->mon_dirty = true;
@@ -883,6 +886,19 @@ swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
     const int threads = c->params.block_threads == 0
                             ? m.block_cells
                             : c->params.block_threads;
+    if (!dt_fixed && !dt_log && !slots) {
+        // plain steps: one launch each, or graph replays (graph_steps)
+        const StepBuffers b{{c->d.h[0], c->d.h[1]},
+                            {c->d.hu[0], c->d.hu[1]},
+                            {c->d.hv[0], c->d.hv[1]}};
+        hipError_t e = enqueue_steps(
+            a, b, c->cur_buf, c->cur_slot, c->step_index, n,
+            StepLaunch{m.block_cells, threads, c->params.load_schedule},
+            &c->graph, c->params.graph_steps, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "step launch");
+        c->t_known = false;
+        return SWE_OK;
+    }
     int64_t logged = 0;   // dt_log entries written
     for (int64_t k = 0; k < n; ++k) {
         if (slots) {

@@ -77,6 +77,7 @@ struct swe_ctx {
     bool mon_dirty = true;     // monitors to be reset before the next step
     double *dt_dev = nullptr;  // time-step schedule (library-allocated)
     int64_t dt_cap = 0;
+    swe::StepGraph graph;      // captured step runs (graph_steps > 0)
 };
 
 namespace swe {

@@ -35,6 +35,9 @@ struct Clock {
     long long pad2;
     // bits of min over wet cells of R_i / s_i, per slot and lane
     unsigned long long minrs[3][kClockLanes][16];
+    // index of the step that reads a slot (launches since the mesh was
+    // set), so that steps replayed from a captured graph know their own
+    long long idx[3];
 };
 
 // Monitors: per boundary slot the outward volume rate of the last step and
@@ -107,7 +110,7 @@ size_t step_lds_bytes(int block_cells);
 hipError_t launch_step(const StepArgs &a, int block_cells, int threads,
                        int schedule, hipStream_t s);
 hipError_t launch_clock_set(Clock *c, double t, long long steps,
-                            hipStream_t s);
+                            long long step_index, hipStream_t s);
 hipError_t launch_slot_reset(Clock *c, int slot, hipStream_t s);
 hipError_t launch_min_rs(const double *h, const double *hu, const double *hv,
                          const double *inradius, int64_t n, double g,
@@ -136,5 +139,44 @@ hipError_t launch_envelope_reset(const double *h, int64_t n, double h_dry,
                                  hipStream_t s);
 
 constexpr int kDiagThreads = 256;
+
+// Ping-pong state buffers of a step loop.
+struct StepBuffers {
+    double *h[2], *hu[2], *hv[2];
+};
+
+// Launch configuration of the step kernel.
+struct StepLaunch {
+    int block_cells, threads, schedule;
+};
+
+// A captured run of `steps` step launches (swe_graph.cpp).
+struct StepGraph {
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int steps = 0;
+    int phase = -1;   // step index mod 6 of the first captured step
+    int buf = -1;     // buffer the first captured step reads
+    int slot = -1;    // clock slot the first captured step reads
+    StepArgs key{};   // arguments at capture (per-step fields aside)
+    StepLaunch launch{};
+    StepGraph() = default;
+    StepGraph(const StepGraph &) = delete;
+    StepGraph &operator=(const StepGraph &) = delete;
+    ~StepGraph();
+    void reset();
+    hipError_t capture(const StepArgs &a, const StepBuffers &b, int buf0,
+                       int slot0, long long index0, int k,
+                       const StepLaunch &l);
+};
+
+// Enqueues n steps of `a` from buffer `buf`, clock slot `slot` and step
+// index `index` (all three advanced), one launch per step, or with graph
+// non-null and k > 0 (a multiple of 6) through replays of a graph of k
+// steps wherever k steps remain.
+hipError_t enqueue_steps(StepArgs &a, const StepBuffers &b, int &buf,
+                         int &slot, long long &index, int64_t n,
+                         const StepLaunch &l, StepGraph *graph, int k,
+                         hipStream_t stream);
 
 }  // namespace swe

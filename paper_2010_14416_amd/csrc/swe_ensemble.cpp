@@ -63,6 +63,7 @@ struct swe_ens {
     int cur_buf = 0;
     int cur_slot = 0;
     long long step_index = 0;
+    swe::StepGraph graph;   // captured step runs (graph_steps > 0)
 };
 
 namespace {
@@ -205,7 +206,7 @@ swe_status ens_prepare(swe_ens *e)
         Clock *ck = e->d.clock + m;
         const int64_t c0 = e->cell_off[m];
         ENSCHK(e, swe::launch_clock_set(ck, e->t_start[m], e->steps_start[m],
-                                        e->stream));
+                                        e->step_index, e->stream));
         ENSCHK(e, swe::launch_min_rs(e->d.h[0] + c0, e->d.hu[0] + c0,
                                      e->d.hv[0] + c0, e->d.inr + c0,
                                      e->n_cells[m], e->params.g,
@@ -504,25 +505,16 @@ swe_status swe_ens_advance(swe_ens *e, int64_t steps, const double *t_end)
                             : e->params.block_threads;
     a.n_blocks = int32_t(e->total_blocks);
     a.blk_base = 0;
-    for (int64_t k = 0; k < steps; ++k) {
-        const int b = e->cur_buf;
-        a.h0 = e->d.h[b];
-        a.hu0 = e->d.hu[b];
-        a.hv0 = e->d.hv[b];
-        a.h1 = e->d.h[b ^ 1];
-        a.hu1 = e->d.hu[b ^ 1];
-        a.hv1 = e->d.hv[b ^ 1];
-        a.cur = e->cur_slot;
-        a.step_index = e->step_index;
-        hipError_t er = swe::launch_step(a, e->block_cells, threads,
-                                         e->params.load_schedule, e->stream);
-        if (er != hipSuccess)
-            return efail(e, SWE_EDEVICE, std::string("step kernel launch: ") +
-                                             hipGetErrorString(er));
-        e->cur_buf ^= 1;
-        e->cur_slot = (e->cur_slot + 1) % 3;
-        ++e->step_index;
-    }
+    const swe::StepBuffers b{{e->d.h[0], e->d.h[1]},
+                             {e->d.hu[0], e->d.hu[1]},
+                             {e->d.hv[0], e->d.hv[1]}};
+    hipError_t er = swe::enqueue_steps(
+        a, b, e->cur_buf, e->cur_slot, e->step_index, steps,
+        swe::StepLaunch{e->block_cells, threads, e->params.load_schedule},
+        &e->graph, e->params.graph_steps, e->stream);
+    if (er != hipSuccess)
+        return efail(e, SWE_EDEVICE,
+                     std::string("step launch: ") + hipGetErrorString(er));
     return SWE_OK;
 }
 

@@ -82,7 +82,8 @@ __device__ __forceinline__ int block_finish(const StepArgs &a, int blk,
                                              double rs, double clamp,
                                              unsigned bad, bool active,
                                              int quiet_steps, bool unbounded,
-                                             double dt, double tn, int nxt,
+                                             double dt, double tn,
+                                             long long idx, int nxt,
                                              double *red_min, double *red_sum,
                                              unsigned *red_bad)
 {
@@ -117,12 +118,13 @@ __device__ __forceinline__ int block_finish(const StepArgs &a, int blk,
         if (cs != 0.0) a.ledger[blk] += cs;
         if (anybad || unbounded) {
             atomicOr(&clock->health, (anybad ? 1u : 0u) | (unbounded ? 2u : 0u));
-            atomicMin(&clock->bad_step, a.step_index);
+            atomicMin(&clock->bad_step, idx);
         }
         if (first) {
             const int nn = nxt == 2 ? 0 : nxt + 1;
             clock->t[nxt] = tn;
-            clock->dt_ring[a.step_index & 7] = dt;
+            clock->idx[nxt] = idx + 1;
+            clock->dt_ring[idx & 7] = dt;
             // the empty steps launched after t_end leave the last time
             // step and the step count alone
             if (dt > 0.0) {
@@ -138,7 +140,8 @@ __device__ __forceinline__ int block_finish(const StepArgs &a, int blk,
 
 // Clock words of this step, read with one vector load per lane so that they
 // travel with the block's first loads: lane x < kClockLanes holds lane x of
-// the time-step minimum, lane kClockLanes the time t.
+// the time-step minimum, lane kClockLanes the time t, lane kClockLanes + 1
+// the step index.
 __device__ __forceinline__ double clock_word(const StepArgs &a,
                                              const Clock *c)
 {
@@ -146,6 +149,7 @@ __device__ __forceinline__ double clock_word(const StepArgs &a,
     if (lane < kClockLanes)
         return __longlong_as_double((long long)c->minrs[a.cur][lane][0]);
     if (lane == kClockLanes) return c->t[a.cur];
+    if (lane == kClockLanes + 1) return __longlong_as_double(c->idx[a.cur]);
     return 0.0;
 }
 
@@ -165,6 +169,7 @@ __device__ __forceinline__ StepTime step_time(const StepArgs &a, double word,
 #pragma unroll
     for (int x = 1; x < kClockLanes; ++x) mrs = fmin(mrs, read_lane(word, x));
     const double t = read_lane(word, kClockLanes);
+    st.idx = __double_as_longlong(read_lane(word, kClockLanes + 1));
     st.dt = fmin(a.cfl * mrs, a.dt_max);
     const double rem = t_end - t;
     if (st.dt >= rem) {
@@ -467,7 +472,8 @@ void swe_step_kernel(StepArgs a)
     }
     const int q = block_finish<NT>(a, blk, clock, first, rs, clamp, bad,
                                    active, quiet_steps, st.unbounded, st.dt,
-                                   st.tn, a.cur == 2 ? 0 : a.cur + 1, red_min,
+                                   st.tn, st.idx, a.cur == 2 ? 0 : a.cur + 1,
+                                   red_min,
                                    red_sum, red_bad);
     {
         // this step's mark is used up; a block not quiet for two steps
@@ -514,12 +520,16 @@ void swe_step_kernel(StepArgs a)
     }
 }
 
-__global__ void clock_set_kernel(Clock *c, double t, long long steps)
+__global__ void clock_set_kernel(Clock *c, double t, long long steps,
+                                 long long step_index)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         c->t[0] = t;
         c->t[1] = t;
         c->t[2] = t;
+        c->idx[0] = step_index;
+        c->idx[1] = step_index;
+        c->idx[2] = step_index;
         for (int s = 0; s < 3; ++s)
             for (int x = 0; x < kClockLanes; ++x) c->minrs[s][x][0] = kInfBits;
         c->last_dt = 0.0;
@@ -756,9 +766,10 @@ hipError_t launch_step(const StepArgs &a, int block_cells, int threads,
 }
 
 hipError_t launch_clock_set(Clock *c, double t, long long steps,
-                            hipStream_t s)
+                            long long step_index, hipStream_t s)
 {
-    hipLaunchKernelGGL(clock_set_kernel, dim3(1), dim3(64), 0, s, c, t, steps);
+    hipLaunchKernelGGL(clock_set_kernel, dim3(1), dim3(64), 0, s, c, t, steps,
+                       step_index);
     return hipGetLastError();
 }
 

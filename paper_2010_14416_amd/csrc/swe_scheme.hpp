@@ -253,6 +253,7 @@ __device__ __forceinline__ Side decode_side(int32_t v)
 // to t_end (the last step lands on t_end exactly); dt = 0 once t >= t_end.
 struct StepTime {
     double dt, tn;
+    long long idx;   // index of this step (from the clock)
     bool unbounded;
 };
 

@@ -47,7 +47,7 @@ class swe_params(C.Structure):
                 ("block_cells", C.c_int32), ("reorder", C.c_int32),
                 ("block_threads", C.c_int32), ("load_schedule", C.c_int32),
                 ("monitors", C.c_int32), ("store_all", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("graph_steps", C.c_int32)]
 
 
 class swe_mesh_stats(C.Structure):

@@ -226,7 +226,7 @@ def test_bad_fields_are_rejected_on_the_host(ctx, field, value, status):
                                         ("block_cells", 100),
                                         ("reorder", 2), ("block_threads", 100),
                                         ("load_schedule", 2),
-                                        ("reserved", 1)])
+                                        ("graph_steps", 5)])
 def test_bad_params_are_rejected(ctx, name, value):
     p = S.swe_default_params()
     setattr(p, name, value)
