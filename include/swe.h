@@ -315,9 +315,11 @@ swe_status swe_advance_dt_noalloc(swe_ctx *ctx, int64_t n, const double *dt,
  * branches the forward run takes (wet/dry, wave-speed cases, star region,
  * reconstruction maximum, positivity fix). Afterwards the context holds the
  * final state, time and ledger of the forward run; monitors are reset.
+ * The forward steps also keep the sum of each cell's edge contributions,
+ * so that the reverse of the cell update needs no second edge evaluation.
  * Needs block_cells = 256; allocates its scratch for the call: about
- * (K + steps / K + 5) x 24 B per cell for K > 1, (steps + 6) x 24 B per
- * cell for K = 1. Synchronises the stream. */
+ * (2 K + steps / K + 4) x 24 B per cell for K > 1, (2 steps + 6) x 24 B
+ * per cell for K = 1. Synchronises the stream. */
 swe_status swe_adjoint_gauges(swe_ctx *ctx, int64_t steps, int32_t n_gauges,
                               const int32_t *gauges, const double *h_target,
                               int32_t checkpoint_every, double *loss,

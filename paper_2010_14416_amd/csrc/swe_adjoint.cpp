@@ -60,11 +60,13 @@ swe_status copy_state(swe_ctx *c, double *dst, bool to_ctx)
     return SWE_OK;
 }
 
-// States held for interval K: every state when K = 1, else the
-// checkpoints, the slots of one segment and the final state.
+// Arrays of 3 n_cells values held for interval K: every state and the
+// summed edge contributions R of every step when K = 1; else the
+// checkpoints, the slots of one segment, the final state and the R of the
+// replayed steps of a segment.
 int64_t states_held(int64_t steps, int64_t K)
 {
-    return K == 1 ? steps + 1 : (steps + K - 1) / K + K + 1;
+    return K == 1 ? 2 * steps + 1 : (steps + K - 1) / K + K + 1 + (K - 1);
 }
 
 int64_t pick_interval(int64_t steps, size_t state_bytes, size_t other_bytes)
@@ -117,7 +119,10 @@ extern "C" swe_status swe_adjoint_gauges(swe_ctx *c, int64_t steps,
                           ? std::min<int64_t>(checkpoint_every, steps)
                           : pick_interval(steps, n_state * 8, other * 8);
     const int64_t nseg = (steps + K - 1) / K;
-    const size_t doubles = size_t(states_held(steps, K)) * n_state + other;
+    // which blocks ran in each forward step (K = 1) or replayed step
+    const size_t log_bytes = size_t(K == 1 ? steps : K) * nb;
+    const size_t doubles = size_t(states_held(steps, K)) * n_state + other +
+                           (log_bytes + 7) / 8;
     DeviceScratch scratch;
     {
         hipError_t e = hipMalloc(&scratch.p, doubles * 8);
@@ -133,13 +138,17 @@ extern "C" swe_status swe_adjoint_gauges(swe_ctx *c, int64_t steps,
     double *ckpt = p;                    p += size_t(nseg) * n_state;
     double *seg = p;                     p += K > 1 ? size_t(K) * n_state : 0;
     double *final_state = p;             p += n_state;
+    // the summed edge contributions of every step (K = 1) or of the
+    // replayed steps of a segment
+    double *r_log = p;   p += size_t(K == 1 ? steps : K - 1) * n_state;
     double *lam[2] = {p, p + n_state};   p += 2 * n_state;
     double *ld = p;                      p += n_state;
     double *lr = p;                      p += n_state;
     double *g_gm2 = p;                   p += n;
     double *g_z = p;                     p += n;
     double *g_m = p;                     p += n;
-    double *ledger_copy = p;
+    double *ledger_copy = p;             p += nb;
+    uint8_t *run_log = (uint8_t *)p;
 
     // forward: ordinary steps, time steps recorded, checkpoints
     if ((st = swe::ctx_dt_buffer(c, steps))) return st;
@@ -147,7 +156,7 @@ extern "C" swe_status swe_adjoint_gauges(swe_ctx *c, int64_t steps,
         if ((st = copy_state(c, ckpt, false))) return st;
         swe::StepArgs a = swe::ctx_step_args(c, INFINITY);
         if ((st = swe::ctx_enqueue(c, a, steps, nullptr, c->dt_dev, ckpt,
-                                   n_state)))
+                                   n_state, run_log, r_log)))
             return st;
     } else {
         for (int64_t s = 0; s < nseg; ++s) {
@@ -222,13 +231,24 @@ extern "C" swe_status swe_adjoint_gauges(swe_ctx *c, int64_t steps,
     };
     for (int64_t s = nseg - 1; s >= 0; --s) {
         const int64_t m = std::min(K, steps - s * K);
+        if (m > 1) {
+            // the quiet counters and run marks describe the state the
+            // context last stepped, not this checkpoint: every block runs
+            // the replay's first two steps, dormant blocks only after that
+            ADJCHK(c, swe::launch_fill_u32((unsigned *)c->d.quiet, 0u,
+                                           int64_t(nb), c->stream));
+            ADJCHK(c, swe::launch_fill_u32(c->d.run, 1u, 2 * int64_t(nb),
+                                           c->stream));
+        }
         for (int64_t j = 0; j + 1 < m; ++j) {
             const double *u = state_at(s, j);
             double *w = state_at(s, j + 1);
             const double *in[3] = {u, u + n, u + 2 * n};
             double *const out[3] = {w, w + n, w + 2 * n};
             if ((st = swe::ctx_step_between(c, in, out,
-                                            dts[size_t(s * K + j)])))
+                                            dts[size_t(s * K + j)],
+                                            run_log + size_t(j) * nb,
+                                            r_log + size_t(j) * n_state)))
                 return st;
         }
         for (int64_t j = m - 1; j >= 0; --j) {
@@ -243,6 +263,13 @@ extern "C" swe_status swe_adjoint_gauges(swe_ctx *c, int64_t steps,
             A.lam_out_hu = lam_next + n;
             A.lam_out_hv = lam_next + 2 * n;
             A.dt = dts[size_t(s * K + j)];
+            // blocks dormant in the forward step (recorded by the forward
+            // for K = 1, by the replay for the others; the segment's last
+            // step was not replayed)
+            A.ran = K == 1 ? run_log + size_t(s) * nb
+                           : (j + 1 < m ? run_log + size_t(j) * nb : nullptr);
+            A.R = K == 1 ? r_log + size_t(s) * n_state
+                         : (j + 1 < m ? r_log + size_t(j) * n_state : nullptr);
             ADJCHK(c, swe::launch_adjoint_step(A, 256, c->stream));
             std::swap(lam_cur, lam_next);
         }

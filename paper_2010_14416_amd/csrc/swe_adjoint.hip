@@ -461,6 +461,20 @@ __device__ __forceinline__ CellState cell_at(const AdjArgs &a, int c)
     return s;
 }
 
+// A block dormant in the forward step whose cells all hold no water
+// (h == 0): its cells took the quiet dry path, every edge touching them
+// added exact zeros, so the reverse step reduces to lambda_h passing
+// through (lambda_hu = lambda_hv = 0) with no gradient. The check of h
+// keeps the shortcut exact even for a quiet cell with a film of water.
+template <int NC>
+__device__ __forceinline__ bool dormant_dry(const AdjArgs &a, int blk,
+                                           bool owner, int i)
+{
+    if (!a.ran || a.ran[blk] != 0) return false;
+    const bool dry = !owner || a.h[i] == 0.0;
+    return __syncthreads_and(dry) != 0;
+}
+
 template <int NC>
 __global__ __launch_bounds__(NC) void adj_cell_kernel(AdjArgs a)
 {
@@ -468,9 +482,22 @@ __global__ __launch_bounds__(NC) void adj_cell_kernel(AdjArgs a)
     __shared__ double s_c[9 * NC];   // [component][side][cell]
     const int tid = threadIdx.x, blk = blockIdx.x;
     const int c0 = blk * NC, nc = min(NC, a.n_cells - c0);
-    const int e0 = a.blk_edge[blk], ne = a.blk_edge[blk + 1] - e0;
     const bool owner = tid < nc;
     const int i = c0 + tid;
+    if (dormant_dry<NC>(a, blk, owner, i)) {
+        // what the cell reverse gives for h = 0 and R = 0 (hn = 0 <= h_dry)
+        if (owner) {
+            const double lh = a.lam_h[i];
+            a.ld_h[i] = lh;
+            a.ld_hu[i] = 0.0;
+            a.ld_hv[i] = 0.0;
+            a.lr_h[i] = a.dt * lh / a.area[i];
+            a.lr_hu[i] = 0.0;
+            a.lr_hv[i] = 0.0;
+        }
+        return;
+    }
+    const int e0 = a.blk_edge[blk], ne = a.blk_edge[blk + 1] - e0;
     const double g = a.g, h_dry = a.h_dry;
     // the block's records first (edges to other blocks come first in the
     // list), then the neighbour of the first edge, as in the forward step
@@ -577,6 +604,44 @@ __global__ __launch_bounds__(NC) void adj_cell_kernel(AdjArgs a)
     if (gm2b != 0.0) a.grad_gm2[i] += gm2b;
 }
 
+// The cell pass when the forward step stored its summed contributions R:
+// the reverse of the cell update from the stored R (the same values the
+// edge evaluation of adj_cell_kernel gives), one thread per cell.
+template <int NC>
+__global__ __launch_bounds__(NC) void adj_cell_stored_kernel(AdjArgs a)
+{
+    const int tid = threadIdx.x, blk = blockIdx.x;
+    const int c0 = blk * NC, nc = min(NC, a.n_cells - c0);
+    const bool owner = tid < nc;
+    const int i = c0 + tid;
+    const bool skip = dormant_dry<NC>(a, blk, owner, i);
+    if (!owner) return;
+    if (skip) {
+        const double lh = a.lam_h[i];
+        a.ld_h[i] = lh;
+        a.ld_hu[i] = 0.0;
+        a.ld_hv[i] = 0.0;
+        a.lr_h[i] = a.dt * lh / a.area[i];
+        a.lr_hu[i] = 0.0;
+        a.lr_hv[i] = 0.0;
+        return;
+    }
+    const double R0 = a.R[i], R1 = a.R[a.n_cells + i],
+                 R2 = a.R[2 * a.n_cells + i];
+    const double h = a.h[i], h_dry = a.h_dry;
+    double hb, hub, hvb, R0b, R1b, R2b, gm2b;
+    cell_update_rev(h_dry, a.dt, a.area[i], h > h_dry ? a.gm2[i] : 0.0, h,
+                    a.hu[i], a.hv[i], R0, R1, R2, a.lam_h[i], a.lam_hu[i],
+                    a.lam_hv[i], hb, hub, hvb, R0b, R1b, R2b, gm2b);
+    a.ld_h[i] = hb;
+    a.ld_hu[i] = hub;
+    a.ld_hv[i] = hvb;
+    a.lr_h[i] = R0b;
+    a.lr_hu[i] = R1b;
+    a.lr_hv[i] = R2b;
+    if (gm2b != 0.0) a.grad_gm2[i] += gm2b;
+}
+
 template <int NC>
 __global__ __launch_bounds__(NC) void adj_edge_kernel(AdjArgs a)
 {
@@ -585,9 +650,17 @@ __global__ __launch_bounds__(NC) void adj_edge_kernel(AdjArgs a)
     __shared__ double s_a[12 * NC];   // [h, hu, hv, z][side][cell]
     const int tid = threadIdx.x, blk = blockIdx.x;
     const int c0 = blk * NC, nc = min(NC, a.n_cells - c0);
-    const int e0 = a.blk_edge[blk], ne = a.blk_edge[blk + 1] - e0;
     const bool owner = tid < nc;
     const int i = c0 + tid;
+    if (dormant_dry<NC>(a, blk, owner, i)) {
+        if (owner) {
+            a.lam_out_h[i] = a.lam_h[i] + 0.0;
+            a.lam_out_hu[i] = 0.0;
+            a.lam_out_hv[i] = 0.0;
+        }
+        return;
+    }
+    const int e0 = a.blk_edge[blk], ne = a.blk_edge[blk + 1] - e0;
     const double g = a.g, h_dry = a.h_dry;
     if (owner) {
         const CellState s = cell_at(a, i);
@@ -687,8 +760,12 @@ hipError_t launch_adjoint_step(const AdjArgs &a, int block_cells,
                                hipStream_t s)
 {
     if (block_cells != 256) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(adj_cell_kernel<256>, dim3(a.n_blocks), dim3(256), 0,
-                       s, a);
+    if (a.R)
+        hipLaunchKernelGGL(adj_cell_stored_kernel<256>, dim3(a.n_blocks),
+                           dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(adj_cell_kernel<256>, dim3(a.n_blocks), dim3(256),
+                           0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(adj_edge_kernel<256>, dim3(a.n_blocks), dim3(256), 0,

@@ -44,6 +44,14 @@ struct AdjArgs {
     // gradients, accumulated over the reverse steps
     double *grad_gm2;
     double *grad_z;
+    // null, or per block 0 if the block was dormant in the forward step
+    // (its cells kept their quiet dry state: lambda_h passes through,
+    // lambda_hu and lambda_hv become 0, no gradient), else 1
+    const uint8_t *ran;
+    // null, or the summed edge contributions R of the forward step (3 x
+    // n_cells, stored by it): the cell pass then reads R instead of
+    // evaluating the block's edges again
+    const double *R;
     double g, h_dry, dt;
     int32_t n_cells;
     int32_t n_blocks;

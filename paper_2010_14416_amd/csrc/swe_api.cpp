@@ -834,7 +834,8 @@ StepArgs ctx_step_args(swe_ctx *c, double t_end)
 }
 
 swe_status ctx_step_between(swe_ctx *c, const double *const in[3],
-                            double *const out[3], double dt)
+                            double *const out[3], double dt,
+                            uint8_t *run_log, double *r_out)
 {
     StepArgs a = ctx_step_args(c, INFINITY);
     a.h0 = in[0];
@@ -845,7 +846,9 @@ swe_status ctx_step_between(swe_ctx *c, const double *const in[3],
     a.hv1 = out[2];
     a.cfl = INFINITY;   // dt = min(cfl * min R/s, dt_max) = dt exactly
     a.dt_max = dt;
-    a.store_all = 1;    // `out` need not hold the state before `in`
+    a.fresh_out = 1;    // `out` need not hold the state before `in`
+    a.run_log = run_log;
+    a.r_out = r_out;
     a.mon = nullptr;
     a.cur = c->cur_slot;
     a.step_index = c->step_index;
@@ -879,14 +882,15 @@ swe_status ctx_dt_buffer(swe_ctx *c, int64_t n)
 
 swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
                        const double *dt_fixed, double *dt_log,
-                       double *slots, size_t stride)
+                       double *slots, size_t stride, uint8_t *run_log,
+                       double *r_log)
 {
     const BlockMesh &m = c->mesh;
     const size_t nc = size_t(m.n_cells);
     const int threads = c->params.block_threads == 0
                             ? m.block_cells
                             : c->params.block_threads;
-    if (!dt_fixed && !dt_log && !slots) {
+    if (!dt_fixed && !dt_log && !slots && !run_log && !r_log) {
         // plain steps: one launch each, or graph replays (graph_steps)
         const StepBuffers b{{c->d.h[0], c->d.h[1]},
                             {c->d.hu[0], c->d.hu[1]},
@@ -910,7 +914,7 @@ swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
             a.h1 = w;
             a.hu1 = w + nc;
             a.hv1 = w + 2 * nc;
-            a.store_all = 1;   // a fresh slot holds no earlier state
+            a.fresh_out = 1;   // a fresh slot holds no earlier state
         } else {
             const int b = c->cur_buf;
             a.h0 = c->d.h[b];
@@ -922,6 +926,9 @@ swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
         }
         a.cur = c->cur_slot;
         a.step_index = c->step_index;
+        a.run_log = run_log ? run_log + size_t(k) * size_t(m.n_blocks)
+                            : nullptr;
+        a.r_out = r_log ? r_log + size_t(k) * 3 * nc : nullptr;
         if (dt_fixed) {
             // dt = min(cfl * min R/s, dt_max) = dt_fixed[k] exactly
             a.cfl = INFINITY;

@@ -92,14 +92,21 @@ StepArgs ctx_step_args(swe_ctx *c, double t_end);
 // with dt_log (device, n values) the time step of step k is copied there.
 // With slots, the steps run outside the ping-pong buffers: step k reads the
 // state at slots + k * stride (h, hu, hv, n_cells values each) and writes
-// every cell of slots + (k + 1) * stride.
+// every cell of slots + (k + 1) * stride. With run_log (device), step k
+// records which blocks ran at run_log + k * n_blocks; with r_log (device),
+// its summed edge contributions at r_log + k * 3 n_cells.
 swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
                        const double *dt_fixed, double *dt_log,
-                       double *slots = nullptr, size_t stride = 0);
+                       double *slots = nullptr, size_t stride = 0,
+                       uint8_t *run_log = nullptr, double *r_log = nullptr);
 // One step from the state arrays `in` (h, hu, hv) into `out`, outside the
-// context's ping-pong buffers, with time step dt (monitors not updated).
+// context's ping-pong buffers, with time step dt (monitors not updated);
+// with run_log (device, n_blocks values), which blocks ran; with r_out
+// (device, 3 n_cells values), the summed edge contributions.
 swe_status ctx_step_between(swe_ctx *c, const double *const in[3],
-                            double *const out[3], double dt);
+                            double *const out[3], double dt,
+                            uint8_t *run_log = nullptr,
+                            double *r_out = nullptr);
 // Argument checks of a frozen-schedule advance (no device use).
 swe_status ctx_advance_dt_check(swe_ctx *c, int64_t n, const double *dt);
 // n steps with the host time steps dt (or the CFL time steps when dt is

@@ -98,6 +98,14 @@ struct StepArgs {
     int32_t n_blocks;         // blocks of this launch, from block blk_base
     int32_t blk_base;
     int32_t store_all;        // 1: every cell stores every step
+    int32_t fresh_out;        // 1: the output holds no earlier state (a
+                              // fresh slot): every cell stores, and a
+                              // dormant block copies its state over
+    uint8_t *run_log;         // null, or per block 1 if it ran this step
+                              // and 0 if it was dormant (for the adjoint)
+    double *r_out;            // null, or per cell the summed edge
+                              // contributions R (3 x n_cells: R_h, R_hu,
+                              // R_hv; zero for dormant blocks)
     int32_t cur;              // clock slot of this step
     long long step_index;
 };

@@ -36,7 +36,8 @@ bool same_fixed_args(const StepArgs &x, const StepArgs &y)
            std::memcmp(&x.dt_max, &y.dt_max, sizeof x.dt_max) == 0 &&
            std::memcmp(&x.t_end, &y.t_end, sizeof x.t_end) == 0 &&
            SAME(n_cells) && SAME(n_blocks) && SAME(blk_base) &&
-           SAME(store_all);
+           SAME(store_all) && SAME(fresh_out) && SAME(run_log) &&
+           SAME(r_out);
 #undef SAME
 }
 

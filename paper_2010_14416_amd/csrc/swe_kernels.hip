@@ -215,8 +215,13 @@ __device__ __forceinline__ int xcd_block(int w, int n_blocks)
 // of an edge between two cells holding no water is never read, and a dry
 // cell reads its area and inscribed radius only if it receives flux.
 // Both read the same values and round identically.
-template <int NC, int NT, bool EAGER, bool MON>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6)))
+// SLOT: the output is a fresh slot (the adjoint's stored states): every cell
+// stores, a dormant block copies its state over, and which blocks ran is
+// recorded in a.run_log (if not null). A separate instantiation, so that
+// the plain step keeps its registers.
+template <int NC, int NT, bool EAGER, bool MON, bool SLOT>
+__global__ __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(SLOT ? 5 : 6)))
 void swe_step_kernel(StepArgs a)
 {
     extern __shared__ double lds[];
@@ -251,7 +256,22 @@ void swe_step_kernel(StepArgs a)
     // one step ago, so it would compute (and already holds) the same quiet
     // results. No block of the previous step marked it to run: it returns
     // before any other load (the clock's block always runs).
-    if (a.skip_dormant && !a.store_all && !first && run_me == 0u) return;
+    if (a.skip_dormant && !a.store_all && !first && run_me == 0u) {
+        if (SLOT && a.run_log && tid == 0) a.run_log[blk] = 0;
+        if (SLOT && tid < NC && blk * NC + tid < cell_end) {
+            // a fresh output slot: carry the unchanged state over
+            const int c = blk * NC + tid;
+            a.h1[c] = a.h0[c];
+            a.hu1[c] = a.hu0[c];
+            a.hv1[c] = a.hv0[c];
+            if (a.r_out) {
+                a.r_out[c] = 0.0;
+                a.r_out[a.n_cells + c] = 0.0;
+                a.r_out[2 * a.n_cells + c] = 0.0;
+            }
+        }
+        return;
+    }
     Clock *clock = a.clock + mem;
     const double t_end = a.t_end_m ? a.t_end_m[mem] : a.t_end;
     const int nc = min(NC, cell_end - c0);
@@ -440,6 +460,11 @@ void swe_step_kernel(StepArgs a)
             R1 += s_c[(3 + k) * NC + tid];
             R2 += s_c[(6 + k) * NC + tid];
         }
+        if (SLOT && a.r_out) {
+            a.r_out[i] = R0;
+            a.r_out[a.n_cells + i] = R1;
+            a.r_out[2 * a.n_cells + i] = R2;
+        }
         hun = hu;
         hvn = hv;
         const double dt = st.dt;
@@ -480,6 +505,7 @@ void swe_step_kernel(StepArgs a)
         // marks itself and its neighbour blocks to run at the next step
         const size_t next = size_t(a.n_blocks) - run_at;
         if (tid == 0 && run_me) a.run[run_at + blk] = 0u;
+        if (SLOT && tid == 0 && a.run_log) a.run_log[blk] = 1;
         if (q < 2) {
             if (tid == 0) a.run[next + blk] = 1u;
             if (tid < kNbrSlots && s_nbr[tid] >= 0)
@@ -490,7 +516,7 @@ void swe_step_kernel(StepArgs a)
     // the wave never waits for its own stores. A quiet cell of a block quiet
     // in the two previous steps already holds (h, 0, 0) in the output buffer
     // (it held U^{n-1} = U^n).
-    if (owner && (active || quiet_steps < 2 || a.store_all)) {
+    if (owner && (active || quiet_steps < 2 || a.store_all || SLOT)) {
         a.h1[i] = hn;
         a.hu1[i] = hun;
         a.hv1[i] = hvn;
@@ -714,26 +740,41 @@ size_t step_lds_bytes(int block_cells)
 }
 
 namespace {
-template <int NC, int NT, bool MON>
+template <int NC, int NT, bool MON, bool SLOT>
 void launch_mon(const StepArgs &a, int schedule, hipStream_t s)
 {
     if (schedule == 0)
-        hipLaunchKernelGGL((swe_step_kernel<NC, NT, false, MON>),
+        hipLaunchKernelGGL((swe_step_kernel<NC, NT, false, MON, SLOT>),
                            dim3(a.n_blocks), dim3(NT), step_lds_bytes(NC), s,
                            a);
     else
-        hipLaunchKernelGGL((swe_step_kernel<NC, NT, true, MON>),
+        hipLaunchKernelGGL((swe_step_kernel<NC, NT, true, MON, SLOT>),
                            dim3(a.n_blocks), dim3(NT), step_lds_bytes(NC), s,
                            a);
 }
 
-template <int NC, int NT>
-void launch_one(const StepArgs &a, int schedule, hipStream_t s)
+template <int NC, int NT, bool SLOT>
+void launch_slot(const StepArgs &a, int schedule, hipStream_t s)
 {
     if (a.mon)
-        launch_mon<NC, NT, true>(a, schedule, s);
+        launch_mon<NC, NT, true, SLOT>(a, schedule, s);
     else
-        launch_mon<NC, NT, false>(a, schedule, s);
+        launch_mon<NC, NT, false, SLOT>(a, schedule, s);
+}
+
+// Steps into fresh slots (the adjoint's) exist for 256-cell blocks only.
+template <int NC, int NT>
+hipError_t launch_one(const StepArgs &a, int schedule, hipStream_t s)
+{
+    if (!a.fresh_out) {
+        launch_slot<NC, NT, false>(a, schedule, s);
+        return hipSuccess;
+    }
+    if constexpr (NC == 256) {
+        launch_slot<NC, NT, true>(a, schedule, s);
+        return hipSuccess;
+    }
+    return hipErrorInvalidValue;
 }
 }  // namespace
 
@@ -742,26 +783,28 @@ hipError_t launch_step(const StepArgs &a, int block_cells, int threads,
 {
     const bool twice = threads == 2 * block_cells;
     if (!twice && threads != block_cells) return hipErrorInvalidValue;
+    hipError_t e;
     switch (block_cells) {
     case 64:
-        twice ? launch_one<64, 128>(a, schedule, s)
-              : launch_one<64, 64>(a, schedule, s);
+        e = twice ? launch_one<64, 128>(a, schedule, s)
+                  : launch_one<64, 64>(a, schedule, s);
         break;
     case 128:
-        twice ? launch_one<128, 256>(a, schedule, s)
-              : launch_one<128, 128>(a, schedule, s);
+        e = twice ? launch_one<128, 256>(a, schedule, s)
+                  : launch_one<128, 128>(a, schedule, s);
         break;
     case 256:
-        twice ? launch_one<256, 512>(a, schedule, s)
-              : launch_one<256, 256>(a, schedule, s);
+        e = twice ? launch_one<256, 512>(a, schedule, s)
+                  : launch_one<256, 256>(a, schedule, s);
         break;
     case 512:
-        twice ? launch_one<512, 1024>(a, schedule, s)
-              : launch_one<512, 512>(a, schedule, s);
+        e = twice ? launch_one<512, 1024>(a, schedule, s)
+                  : launch_one<512, 512>(a, schedule, s);
         break;
     default:
         return hipErrorInvalidValue;
     }
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

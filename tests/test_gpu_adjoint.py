@@ -166,6 +166,13 @@ def test_full_size_canal_gradients_and_checkpoints():
     say(f"[adjoint full] {case.n_cells} cells, {steps} steps")
     a = solver(case)
     loss, gm, gz = S.swe_adjoint_gauges(a.ctx, steps, gauges, target)
+    # the forward with every state kept (each step into a fresh slot,
+    # dormant blocks copying their state over) ends where a plain run does
+    ref = solver(case)
+    S.swe_advance_dt(ref.ctx, steps, dts)
+    for x, y in zip(a.state(), ref.state()):
+        assert np.array_equal(x, y)
+    ref.close()
     a.close()
     b = solver(case)
     l2, gm2, gz2 = S.swe_adjoint_gauges(b.ctx, steps, gauges, target,
