@@ -71,9 +71,9 @@ def make_case(args):
     return W.dam_break_canal(), "dam-break-canal-4k: 100x20 squares"
 
 
-def traffic_per_launch(workload_name, n_cells):
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    summary, if it was taken on this kernel source and workload size."""
+def counter_record(n_cells):
+    """The committed rocprofv3 counter summary of the step kernel, if it was
+    taken on this kernel source and a workload of this size (else None)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -82,7 +82,20 @@ def traffic_per_launch(workload_name, n_cells):
     if t.get("kernel_sha256") != kernel_hash() or \
             t.get("n_cells") != n_cells:
         return None
-    return t.get("bytes_per_launch")
+    return t
+
+
+def ev_time(stream, fn):
+    """Milliseconds of the work `fn` enqueues on `stream` (HIP events)."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
 
 
 def copy_bandwidth(mb, reps=5):
@@ -108,22 +121,60 @@ def copy_bandwidth(mb, reps=5):
     return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(case, seconds, threads):
-    import oracle
-    o = oracle.Oracle(case, threads=threads)
+def cpu_model():
+    """Host CPU model from /proc/cpuinfo (None if unreadable)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_sample(o, n_cells, seconds, min_steps=1, max_steps=200):
+    """Oracle steps until `seconds` have passed (at least min_steps);
+    returns (cell-updates/s, steps, seconds)."""
     steps = 0
     t0 = time.perf_counter()
     while True:
         o.run(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= seconds or steps >= 200:
+        if (el >= seconds and steps >= min_steps) or steps >= max_steps:
             break
-    return dict(value=case.n_cells * steps / el, unit="cell-updates/s",
-                cores=threads, kind="oracle",
-                sample=f"{steps} oracle steps from the initial state of the "
-                       f"same {case.n_cells}-cell workload ({el:.1f} s, "
-                       f"setup excluded)")
+    return n_cells * steps / el, steps, el
+
+
+def cpu_baseline(case, seconds, threads, samples=3, single_steps=10):
+    """The FP64 oracle on the host: the median of `samples` timed samples
+    of about `seconds` each on `threads` threads, and one sample of at
+    least `single_steps` steps on one thread. Set-up excluded; the samples
+    continue one run from the workload's initial state."""
+    import oracle
+    o = oracle.Oracle(case, threads=threads)
+    vals, desc = [], []
+    for _ in range(samples):
+        v, n, el = cpu_sample(o, case.n_cells, seconds)
+        vals.append(v)
+        desc.append(f"{n} steps in {el:.1f} s")
+    del o
+    out = dict(value=float(np.median(vals)), unit="cell-updates/s",
+               cores=threads, kind="oracle",
+               sample=f"median of {samples} samples of oracle steps on the "
+                      f"same {case.n_cells}-cell workload, continuing one "
+                      f"run from its initial state ({'; '.join(desc)}; "
+                      f"set-up excluded)",
+               samples=vals, cpu_model=cpu_model())
+    if threads > 1 and single_steps > 0:
+        o1 = oracle.Oracle(case, threads=1)
+        v, n, el = cpu_sample(o1, case.n_cells, 0.0, min_steps=single_steps,
+                              max_steps=single_steps)
+        out["single_core_value"] = v
+        out["single_core_sample"] = (f"{n} oracle steps from the initial "
+                                     f"state on one thread ({el:.1f} s)")
+    return out
 
 
 def _read_counter_csv(path, counter):
@@ -140,15 +191,23 @@ def _read_counter_csv(path, counter):
     return out
 
 
-def pmc_summary(fetch_csv, write_csv, copy_mb, n_cells, out_path):
-    """Per-launch HBM traffic of the step kernel from two rocprofv3 --pmc runs
-    (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by the ratio of
-    known to counted bytes of the reference streaming kernel."""
+def pmc_summary(fetch_csv, write_csv, copy_mb, n_cells, out_path,
+                valu_csv=None, steps=""):
+    """Per-launch HBM traffic of the step kernel from two rocprofv3 --pmc
+    runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by the
+    ratio of known to counted bytes of the reference streaming kernel; with
+    valu_csv, the VALU counters of a third run (SQ_INSTS_VALU,
+    SQ_INSTS_VALU_TRANS_F64, SQ_BUSY_CU_CYCLES): instructions per launch and
+    the share of the kernel's cycles a SIMD spends issuing them (4 cycles
+    per wave64 instruction, 16 for the quarter-rate FP64 transcendentals,
+    1 024 SIMDs; SQ_BUSY_CU_CYCLES summed over the 256 CUs)."""
     fetch = _read_counter_csv(fetch_csv, "FETCH_SIZE")
     write = _read_counter_csv(write_csv, "WRITE_SIZE")
 
     def pick(d, key):
-        ks = [k for k in d if key in k]
+        # the plain step, not its fresh-slot instantiation (the adjoint's)
+        ks = [k for k in d if key in k and not re.search(
+            r"swe_step_kernel<\d+, \d+, \w+, \w+, true>", k)]
         if not ks:
             raise SystemExit(f"no dispatch of a kernel matching {key!r}")
         vals = [v for k in ks for v in d[k]]
@@ -161,7 +220,7 @@ def pmc_summary(fetch_csv, write_csv, copy_mb, n_cells, out_path):
     f_kib, nf = pick(fetch, "swe_step_kernel")
     w_kib, nw = pick(write, "swe_step_kernel")
     res = dict(kernel="swe_step_kernel", kernel_sha256=kernel_hash(),
-               n_cells=n_cells,
+               n_cells=n_cells, steps=steps,
                fetch_kib_per_launch=f_kib, write_kib_per_launch=w_kib,
                dispatches=dict(fetch=nf, write=nw),
                reference=dict(kernel="torch neg (elementwise, float64)",
@@ -173,6 +232,16 @@ def pmc_summary(fetch_csv, write_csv, copy_mb, n_cells, out_path):
     res["bytes_per_launch"] = (res["fetch_bytes_per_launch"] +
                                res["write_bytes_per_launch"])
     res["bytes_per_cell"] = res["bytes_per_launch"] / n_cells
+    if valu_csv:
+        v = {c: pick(_read_counter_csv(valu_csv, c), "swe_step_kernel")[0]
+             for c in ("SQ_INSTS_VALU", "SQ_INSTS_VALU_TRANS_F64",
+                       "SQ_BUSY_CU_CYCLES")}
+        issue = (4 * v["SQ_INSTS_VALU"] +
+                 12 * v["SQ_INSTS_VALU_TRANS_F64"]) / 1024
+        res["valu"] = dict(insts_per_launch=v["SQ_INSTS_VALU"],
+                           trans_f64_per_launch=v["SQ_INSTS_VALU_TRANS_F64"],
+                           busy_cu_cycles=v["SQ_BUSY_CU_CYCLES"],
+                           issue_frac=issue / (v["SQ_BUSY_CU_CYCLES"] / 256))
     with open(out_path, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res, indent=1))
@@ -188,17 +257,26 @@ def main():
                     choices=["river", "bumps", "canal", "ensemble",
                              "adjoint"])
     ap.add_argument("--cells", type=int, default=13_000_000)
+    ap.add_argument("--run-steps", type=int, default=1000,
+                    help="step count of the workload's run: the steps after "
+                         "the timed ones are also timed (run average)")
     ap.add_argument("--block-cells", type=int, default=None,
-                    help="cells per block (default: 256; 64 for the "
-                         "ensemble, whose members run alone keep 256)")
+                    help="cells per block (default: 256; the ensemble's "
+                         "autotuner picks its own)")
     ap.add_argument("--block-threads", type=int, default=0,
                     help="0: automatic (= block cells)")
     ap.add_argument("--workers", type=int,
                     default=min(16, os.cpu_count() or 1))
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=4.0,
+                    help="length of each of the 3 multi-thread oracle "
+                         "samples")
+    ap.add_argument("--cpu-single-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=2048,
                     help="size of the reference copy (0: skip)")
+    ap.add_argument("--legs", default="small,ensemble,adjoint",
+                    help="extra legs of the default run, comma list of "
+                         "small, ensemble, adjoint (empty: none)")
     ap.add_argument("--sweep", default="",
                     help="comma list of CELLSxTHREADS[sSCHEDULE][mMONITORS]"
                          "[aSTORE_ALL] variants to time on the same mesh "
@@ -208,6 +286,13 @@ def main():
                                                         "WRITE_CSV"),
                     help="write the step kernel's traffic summary from two "
                          "rocprofv3 counter CSVs and exit (no GPU needed)")
+    ap.add_argument("--pmc-valu", default=None,
+                    help="with --pmc-summary: a third counter CSV with "
+                         "SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F64, "
+                         "SQ_ACTIVE_INST_VALU, SQ_BUSY_CU_CYCLES")
+    ap.add_argument("--pmc-steps", default="",
+                    help="with --pmc-summary: which steps the counter runs "
+                         "covered (recorded in the summary)")
     ap.add_argument("--pmc-out", default=TRAFFIC_FILE)
     ap.add_argument("--pmc-cells", type=int, default=13_004_176,
                     help="cell count of the profiled workload")
@@ -215,6 +300,8 @@ def main():
                     help="ensemble members (--workload ensemble)")
     ap.add_argument("--solo-sample", type=int, default=16,
                     help="ensemble members also timed one at a time")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="ensemble: 64-cell blocks, band 2, no tuning")
     ap.add_argument("--no-every-block", action="store_true",
                     help="skip the second timing with every block computed "
                          "and stored (store_all = 1)")
@@ -222,12 +309,15 @@ def main():
                     help="dry cells within this many edge-steps of a wet "
                          "cell form their own group (swe_set_wet_cells); "
                          "default: the library's choice (2 from a million "
-                         "cells on, else 0; 2 for ensemble members)")
+                         "cells on, else 0)")
     ap.add_argument("--no-group-wet", action="store_true",
                     help="order cells along the curve only, without first "
                          "grouping the initially wet cells apart")
     ap.add_argument("--fd-directions", type=int, default=32,
                     help="finite-difference checks of the adjoint")
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="steps per captured HIP graph (0: one launch per "
+                         "step)")
 
     args = ap.parse_args()
     if args.steps is None:
@@ -236,7 +326,8 @@ def main():
 
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_mb,
-                    args.pmc_cells, args.pmc_out)
+                    args.pmc_cells, args.pmc_out, args.pmc_valu,
+                    args.pmc_steps)
         return
 
     if args.gpus != 1:
@@ -245,242 +336,346 @@ def main():
               file=sys.stderr, flush=True)
         sys.exit(2)
 
-    import torch
-    from paper_2010_14416_amd import Solver
+    import torch  # noqa: F401
 
     if args.workload == "ensemble":
-        run_ensemble(args)
+        out = base_line(args)
+        ens = leg_ensemble(args, steps=args.steps, warmup=args.warmup,
+                           solo=args.solo_sample, tune=not args.no_autotune)
+        out.update(value=ens["value"], ms_per_step=ens["ensemble_ms"] /
+                   args.steps, config=ens.pop("config"),
+                   roofline=ens.pop("roofline"), ensemble=ens)
+        print(json.dumps(out), flush=True)
         return
     if args.workload == "adjoint":
-        run_adjoint(args)
+        out = base_line(args)
+        adj = leg_adjoint(args, fd_dirs=args.fd_directions)
+        out.update(value=adj.pop("value"), steps=adj["steps"],
+                   ms_per_step=adj.pop("ms_per_step"),
+                   config=adj.pop("config"), adjoint=adj)
+        print(json.dumps(out), flush=True)
         return
+    out = run_main(args)
+    legs = [x for x in args.legs.split(",") if x] if \
+        args.workload == "river" else []
+    if "small" in legs:
+        out["small_mesh"] = leg_small(args)
+    if "ensemble" in legs:
+        ens = leg_ensemble(args, steps=100, warmup=10, solo=8, tune=True,
+                           tune_sample=24, tune_steps=10)
+        ens.pop("config")
+        ens.pop("roofline")
+        out["ensemble"] = ens
+    if "adjoint" in legs:
+        adj = leg_adjoint(args, fd_dirs=8)
+        for k in ("value", "ms_per_step", "config"):
+            adj.pop(k)
+        out["adjoint"] = adj
+    print(json.dumps(out), flush=True)
+
+
+def base_line(args):
+    return dict(metric=METRIC, value=None, unit="cell-updates/s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=None,
+                higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f64", data="synthetic", config=None, roofline=None,
+                cpu_baseline=None)
+
+
+def run_main(args):
+    """The step on one mesh: K timed steps after W warm-up steps, the rest
+    of the workload's run, every block computed, which blocks ran, the
+    roofline and the oracle on the host."""
+    from paper_2010_14416_amd import Solver, swe as S
     t0 = time.perf_counter()
     case, desc = make_case(args)
     log(f"workload {case.name}: {case.n_cells} cells "
         f"({time.perf_counter() - t0:.1f} s to generate)")
     for shape in filter(None, args.sweep.split(",")):
-        m = re.fullmatch(r"(\d+)x(\d+)(?:s(\d))?(?:m(\d))?(?:a(\d))?",
-                         shape.lower())
-        if not m:
-            raise SystemExit(f"bad sweep entry {shape!r}")
-        bc, bt = int(m.group(1)), int(m.group(2))
-        sched, mon, sall = (int(m.group(k) or 0) for k in (3, 4, 5))
-        sw = Solver(case, device=0, block_cells=bc,
-                    group_wet=not args.no_group_wet, wet_band=args.wet_band,
-                    params={"block_threads": bt, "load_schedule": sched,
-                            "monitors": mon, "store_all": sall})
-        sw.advance(args.warmup + 1, want_time=True)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(sw.stream)
-        sw.advance(args.steps)
-        e1.record(sw.stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
-        sw.time()
-        log(f"sweep {bc}x{bt} schedule {sched} monitors {mon} store_all "
-            f"{sall}: {ms:.4f} ms/step, "
-            f"{case.n_cells / (ms * 1e-3):.4e} cell-updates/s, "
-            f"{ALG_BYTES_PER_CELL * case.n_cells / (ms * 1e-3) / 1e9:.0f} "
-            f"GB/s algorithmic")
-        sw.close()
-        del sw
+        sweep_one(args, case, shape)
+
+    def solver(**params):
+        p = {"block_threads": args.block_threads,
+             "graph_steps": args.graph_steps}
+        p.update(params)
+        return Solver(case, device=0, block_cells=args.block_cells or 256,
+                      group_wet=not args.no_group_wet,
+                      wet_band=args.wet_band, params=p)
 
     t0 = time.perf_counter()
-    s = Solver(case, device=0, block_cells=args.block_cells or 256,
-               group_wet=not args.no_group_wet, wet_band=args.wet_band,
-               params={"block_threads": args.block_threads})
+    s = solver()
     info = s.info()
     s.advance(1, want_time=True)          # device set-up + first step
     setup_s = time.perf_counter() - t0
     log(f"set-up {setup_s:.1f} s, {info['n_blocks']} blocks, "
         f"{info['n_block_edges']} block edges")
-    s.advance(args.warmup, want_time=True)
-    stream = s.stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    s.advance(args.steps)                 # enqueue only; no host sync
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    elapsed_ms = ev0.elapsed_time(ev1)
-    t_sim, last_dt, step = s.time()       # also raises on a numeric fault
-    log(f"{args.steps} steps in {elapsed_ms:.2f} ms; t = {t_sim:.4f} s, "
-        f"dt = {last_dt:.4g} s")
-    # the same steps with every block computed and stored (store_all = 1:
-    # no dormant blocks skipped, no quiet stores skipped); same results
-    every_ms = None
-    if not args.no_every_block:
-        s.close()
-        s = Solver(case, device=0, block_cells=args.block_cells or 256,
-                   group_wet=not args.no_group_wet, wet_band=args.wet_band,
-                   params={"block_threads": args.block_threads,
-                           "store_all": 1})
-        s.advance(args.warmup + 1, want_time=True)
-        torch.cuda.synchronize()
-        ev0.record(s.stream)
-        s.advance(args.steps)
-        ev1.record(s.stream)
-        torch.cuda.synchronize()
-        every_ms = ev0.elapsed_time(ev1) / args.steps
-        s.time()
-        log(f"every block computed: {every_ms:.4f} ms per step")
-
+    # the reference copy runs right before the warm-up steps: the GPU is
+    # busy, not idle from the host-side set-up, when the timed steps start
     copy_gbs = None
     if args.copy_mb > 0:
         copy_gbs = copy_bandwidth(args.copy_mb)
         log(f"reference copy of {args.copy_mb} MiB: {copy_gbs:.0f} GB/s")
-
+    s.advance(args.warmup, want_time=True)
+    elapsed_ms = ev_time(s.stream, lambda: s.advance(args.steps))
+    t_sim, last_dt, step = s.time()       # also raises on a numeric fault
+    log(f"{args.steps} steps in {elapsed_ms:.2f} ms; t = {t_sim:.4f} s, "
+        f"dt = {last_dt:.4g} s")
+    # the rest of the workload's run, timed apart: the average over the run
+    done = 1 + args.warmup + args.steps
+    rest = max(0, args.run_steps - done)
+    run_ms = None
+    if rest > 0:
+        rest_ms = ev_time(s.stream, lambda: s.advance(rest))
+        s.time()
+        run_ms = (elapsed_ms + rest_ms) / (args.steps + rest)
+        log(f"steps {1 + args.warmup}..{args.run_steps}: {run_ms:.4f} ms "
+            "per step")
+    s.close()
+    # the same steps with every block computed and stored (store_all = 1:
+    # no dormant blocks skipped, no quiet stores skipped); same results
+    every_ms = None
+    if not args.no_every_block:
+        s = solver(store_all=1)
+        s.advance(1 + args.warmup, want_time=True)
+        every_ms = ev_time(s.stream, lambda: s.advance(args.steps)) / \
+            args.steps
+        s.time()
+        s.close()
+        log(f"every block computed: {every_ms:.4f} ms per step")
+    # which blocks the timed steps computed (the same steps again, one at a
+    # time, each preceded by a count of the blocks marked to run)
+    s = solver()
+    s.advance(1 + args.warmup, want_time=True)
+    run_cells, run_blocks = [], []
+    for k in range(max(args.steps, args.run_steps - 1 - args.warmup)):
+        b, c = S.swe_get_activity(s.ctx)
+        run_blocks.append(b)
+        run_cells.append(c)
+        s.advance(1)
+    s.close()
     n = case.n_cells
+    nb = info["n_blocks"]
+    cells_timed = float(np.mean(run_cells[:args.steps]))
+    blocks_timed = float(np.mean(run_blocks[:args.steps]))
+    log(f"blocks computed per timed step: {blocks_timed:.0f} of {nb} "
+        f"({blocks_timed / nb:.3f}); over the run "
+        f"{np.mean(run_blocks) / nb:.3f}")
+
     ms_per_step = elapsed_ms / args.steps
     value = n * args.steps / (elapsed_ms * 1e-3)
-    alg_bytes = ALG_BYTES_PER_CELL * n
-    achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
-    roofline = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS,
-                    unit="GB/s", frac=achieved / PEAK_HBM_GBS,
-                    traffic=traffic_per_launch(case.name, n),
-                    copy_gbs=copy_gbs)
+    achieved = ALG_BYTES_PER_CELL * cells_timed / (ms_per_step * 1e-3) / 1e9
+    effective = ALG_BYTES_PER_CELL * n / (ms_per_step * 1e-3) / 1e9
+    rec = counter_record(n)
+    traffic = rec.get("bytes_per_launch") if rec else None
+    roofline = dict(
+        bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
+        frac=achieved / PEAK_HBM_GBS, traffic=traffic,
+        alg_bytes_per_launch=ALG_BYTES_PER_CELL * cells_timed,
+        cells_computed_per_launch=cells_timed,
+        blocks_computed_frac=blocks_timed / nb,
+        effective_gbs_all_cells=effective,
+        traffic_gbs=(traffic / (ms_per_step * 1e-3) / 1e9
+                     if traffic else None),
+        traffic_frac=(traffic / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS
+                      if traffic else None),
+        traffic_steps=rec.get("steps") if rec else None,
+        copy_gbs=copy_gbs)
+    if rec and rec.get("valu"):
+        v = rec["valu"]
+        roofline["valu"] = dict(
+            bound="valu", insts_per_launch=v.get("insts_per_launch"),
+            issue_frac=v.get("issue_frac"), steps=rec.get("steps"))
+    if every_ms:
+        roofline["every_block"] = dict(
+            ms_per_step=every_ms,
+            achieved=ALG_BYTES_PER_CELL * n / (every_ms * 1e-3) / 1e9,
+            frac=ALG_BYTES_PER_CELL * n / (every_ms * 1e-3) / 1e9 /
+            PEAK_HBM_GBS)
 
     base = None
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", 0) or
                       (os.cpu_count() or 1))
         log(f"cpu baseline: oracle on {threads} threads")
-        base = cpu_baseline(case, args.cpu_seconds, threads)
-        log(f"cpu baseline {base['value']:.3e} cell-updates/s")
-        if threads > 1:
-            # the same oracle on one core, a shorter sample
-            one = cpu_baseline(case, min(10.0, args.cpu_seconds), 1)
-            base["single_core_value"] = one["value"]
-            base["single_core_sample"] = one["sample"]
-            log(f"cpu baseline, one core: {one['value']:.3e} "
-                f"cell-updates/s")
+        base = cpu_baseline(case, args.cpu_seconds, threads,
+                            single_steps=args.cpu_single_steps)
+        log(f"cpu baseline {base['value']:.3e} cell-updates/s (median), "
+            f"one core {base.get('single_core_value', 0):.3e}")
 
-    out = dict(
-        metric=METRIC, value=value, unit="cell-updates/s", n_gpus=1,
-        steps=args.steps, warmup=args.warmup, ms_per_step=ms_per_step,
-        higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f64", data="synthetic",
+    out = base_line(args)
+    out.update(
+        value=value, ms_per_step=ms_per_step,
         config=dict(workload=desc, n_cells=n, n_edges=info["n_edges"],
                     block_cells=info["block_cells"],
                     block_threads=args.block_threads or info["block_cells"],
+                    graph_steps=args.graph_steps,
                     setup_s=round(setup_s, 2),
-                    effective_gbs=achieved,
+                    timed_steps=f"{1 + args.warmup}..{done - 1}",
+                    run_ms_per_step=run_ms,
+                    run_steps=args.run_steps,
                     every_block_ms_per_step=every_ms),
         roofline=roofline, cpu_baseline=base)
-    print(json.dumps(out), flush=True)
-    s.close()
+    return out
 
 
-def run_ensemble(args):
-    """Batched ensemble of river runs (one launch per step for all members,
-    each with its own time step) against the same members advanced one at a
-    time: the per-member time of a sample of members run alone, scaled to
-    all members, over the ensemble's time."""
-    import torch
+def sweep_one(args, case, shape):
+    from paper_2010_14416_amd import Solver
+    m = re.fullmatch(r"(\d+)x(\d+)(?:s(\d))?(?:m(\d))?(?:a(\d))?",
+                     shape.lower())
+    if not m:
+        raise SystemExit(f"bad sweep entry {shape!r}")
+    bc, bt = int(m.group(1)), int(m.group(2))
+    sched, mon, sall = (int(m.group(k) or 0) for k in (3, 4, 5))
+    sw = Solver(case, device=0, block_cells=bc,
+                group_wet=not args.no_group_wet, wet_band=args.wet_band,
+                params={"block_threads": bt, "load_schedule": sched,
+                        "monitors": mon, "store_all": sall})
+    sw.advance(args.warmup + 1, want_time=True)
+    ms = ev_time(sw.stream, lambda: sw.advance(args.steps)) / args.steps
+    sw.time()
+    log(f"sweep {bc}x{bt} schedule {sched} monitors {mon} store_all "
+        f"{sall}: {ms:.4f} ms/step, "
+        f"{case.n_cells / (ms * 1e-3):.4e} cell-updates/s, "
+        f"{ALG_BYTES_PER_CELL * case.n_cells / (ms * 1e-3) / 1e9:.0f} "
+        f"GB/s algorithmic")
+    sw.close()
+
+
+def leg_small(args, steps=1000, graph_steps=96):
+    """The 4 000-cell dam-break canal, launch-bound: one launch per step
+    against graph replays of `graph_steps` steps (same results)."""
     import workloads as W
-    from paper_2010_14416_amd import Ensemble, Solver
+    from paper_2010_14416_amd import Solver
+    case = W.dam_break_canal()
+    res = {}
+    for k in (0, graph_steps):
+        s = Solver(case, device=0, params={"graph_steps": k})
+        s.advance(2 * max(k, 20), want_time=True)   # includes the capture
+        res[k] = ev_time(s.stream, lambda: s.advance(steps)) / steps
+        s.time()
+        s.close()
+    log(f"canal 4 000 cells: {res[0] * 1e3:.2f} us per step one launch "
+        f"each, {res[graph_steps] * 1e3:.2f} us with graphs of "
+        f"{graph_steps} steps")
+    return dict(workload="dam-break canal, 4 000 cells", steps=steps,
+                ms_per_step_launches=res[0],
+                ms_per_step_graph=res[graph_steps],
+                graph_steps=graph_steps,
+                speedup=res[0] / res[graph_steps])
 
+
+def leg_ensemble(args, steps, warmup, solo, tune, tune_sample=32,
+                 tune_steps=20):
+    """Batched ensemble of 256 river runs (one launch per step for all
+    members, each with its own time step), launch shape picked by the
+    autotuner on a sample of the members, against the same members run
+    one at a time with the plain solver (one launch per step, and graph
+    replays)."""
+    import workloads as W
+    from paper_2010_14416_amd import Ensemble, Solver, swe as S
     t0 = time.perf_counter()
-    cases = W.ensemble_members(n_members=args.members, steps=args.steps,
+    cases = W.ensemble_members(n_members=args.members, steps=500,
                                workers=args.workers)
     n = sum(c.n_cells for c in cases)
     log(f"ensemble: {len(cases)} members, {n} cells "
         f"({time.perf_counter() - t0:.1f} s to generate)")
+    best, table = (64, 2), {}
+    if tune:
+        t0 = time.perf_counter()
+        best, table = S.autotune_ensemble(cases, sample=tune_sample,
+                                          warmup=5, steps=tune_steps)
+        log(f"autotuner ({time.perf_counter() - t0:.1f} s): "
+            + ", ".join(f"{bc}/{b}: {ms:.4f} ms" for (bc, b), ms in
+                        sorted(table.items())) + f"; best {best}")
     t1 = time.perf_counter()
-    ens = Ensemble(cases, block_cells=args.block_cells or 64,
+    ens = Ensemble(cases, block_cells=best[0], wet_band=best[1],
                    group_wet=not args.no_group_wet,
-                   wet_band=2 if args.wet_band is None else args.wet_band,
                    params={"block_threads": args.block_threads})
-    ens.advance(args.warmup)
+    ens.advance(warmup)
     ens.time(0)
     setup_s = time.perf_counter() - t1
     info = ens.info()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(ens.stream)
-    ens.advance(args.steps)
-    ev1.record(ens.stream)
-    torch.cuda.synchronize()
-    ens_ms = ev0.elapsed_time(ev1)
+    ens_ms = ev_time(ens.stream, lambda: ens.advance(steps))
     for k in range(len(cases)):
         ens.time(k)                       # raises on a numeric fault
-    log(f"ensemble: {args.steps} steps in {ens_ms:.2f} ms "
-        f"({info['n_blocks']} blocks)")
     ens.close()
-
-    k_sample = max(1, min(args.solo_sample, len(cases)))
+    log(f"ensemble: {steps} steps in {ens_ms:.2f} ms ({info['n_blocks']} "
+        "blocks)")
+    k_sample = max(1, min(solo, len(cases)))
     pick = np.linspace(0, len(cases) - 1, k_sample).round().astype(int)
-    solo_ms, solo_cells = [], 0
+    solo_ms = {0: [], 96: []}
     for k in pick:
-        s = Solver(cases[k], device=0, block_cells=args.block_cells or 256,
-                   group_wet=not args.no_group_wet, wet_band=args.wet_band,
-                   params={"block_threads": args.block_threads})
-        s.advance(args.warmup, want_time=True)
-        torch.cuda.synchronize()
-        ev0.record(s.stream)
-        s.advance(args.steps)
-        ev1.record(s.stream)
-        torch.cuda.synchronize()
-        solo_ms.append(ev0.elapsed_time(ev1))
-        solo_cells += cases[k].n_cells
-        s.time()
-        s.close()
-    # one at a time, every member: the sample's time per cell-step scaled to
-    # all cells, and the sample's mean time per member
-    per_member_ms = float(np.mean(solo_ms))
-    solo_total_ms = per_member_ms * len(cases)
-    log(f"one at a time: {k_sample} members, {per_member_ms:.2f} ms each "
-        f"for {args.steps} steps")
-    value = n * args.steps / (ens_ms * 1e-3)
-    ms_per_step = ens_ms / args.steps
-    achieved = ALG_BYTES_PER_CELL * n / (ms_per_step * 1e-3) / 1e9
-    out = dict(
-        metric=METRIC, value=value, unit="cell-updates/s", n_gpus=1,
-        steps=args.steps, warmup=args.warmup, ms_per_step=ms_per_step,
-        higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f64", data="synthetic",
+        for g in (0, 96):
+            s = Solver(cases[k], device=0, params={"graph_steps": g})
+            s.advance(max(warmup, 2 * g), want_time=True)
+            solo_ms[g].append(ev_time(s.stream, lambda: s.advance(steps)))
+            s.time()
+            s.close()
+    per = {g: float(np.mean(v)) for g, v in solo_ms.items()}
+    log(f"one at a time: {k_sample} members, {per[0]:.2f} ms each for "
+        f"{steps} steps ({per[96]:.2f} ms with graphs)")
+    value = n * steps / (ens_ms * 1e-3)
+    ms_per_step = ens_ms / steps
+    eff = ALG_BYTES_PER_CELL * n / (ms_per_step * 1e-3) / 1e9
+    return dict(
+        value=value, members=len(cases), n_cells=n, steps=steps,
+        ensemble_ms=ens_ms, ms_per_step=ms_per_step,
+        block_cells=best[0], wet_band=best[1],
+        autotune={f"{bc}x{b}": ms for (bc, b), ms in table.items()},
+        autotune_sample=tune_sample if tune else 0,
+        one_at_a_time_ms_per_member=per[0],
+        one_at_a_time_ms_per_member_graph=per[96],
+        sampled_members=int(k_sample),
+        speedup_vs_one_at_a_time=per[0] * len(cases) / ens_ms,
+        speedup_vs_one_at_a_time_graph=per[96] * len(cases) / ens_ms,
         config=dict(workload=f"ensemble-{len(cases)}: river runs of "
                     "U[10k,200k] cells, Manning U[0.02,0.05], inflow "
                     "U[200,800] m^3/s, own time step each",
-                    n_cells=n, members=len(cases), n_blocks=info["n_blocks"],
-                    setup_s=round(setup_s, 2), effective_gbs=achieved),
-        roofline=dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS,
-                      unit="GB/s", frac=achieved / PEAK_HBM_GBS,
-                      traffic=None, copy_gbs=None),
-        ensemble=dict(one_at_a_time_ms=solo_total_ms,
-                      one_at_a_time_ms_per_member=per_member_ms,
-                      sampled_members=int(k_sample),
-                      ensemble_ms=ens_ms,
-                      speedup_vs_one_at_a_time=solo_total_ms / ens_ms),
-        cpu_baseline=None)
-    print(json.dumps(out), flush=True)
+                    n_cells=n, members=len(cases),
+                    n_blocks=info["n_blocks"], setup_s=round(setup_s, 2),
+                    effective_gbs=eff),
+        roofline=dict(bound="hbm", achieved=eff, peak=PEAK_HBM_GBS,
+                      unit="GB/s", frac=eff / PEAK_HBM_GBS, traffic=None,
+                      note="140 B x every cell of every member per step"))
 
 
-def run_adjoint(args):
+def smooth_direction(case, rng):
+    """A seeded smooth field sin(2 pi kx x + a) cos(2 pi ky y + b) on the
+    canal's cell centroids (x, y scaled to [0, 1])."""
+    c = case.xy[case.tri].mean(axis=1)
+    x = (c - c.min(axis=0)) / (c.max(axis=0) - c.min(axis=0))
+    kx, ky = rng.integers(1, 4, 2)
+    return np.sin(2 * np.pi * kx * x[:, 0] + rng.uniform(0, 6)) * np.cos(
+        2 * np.pi * ky * x[:, 1] + rng.uniform(0, 6))
+
+
+def leg_adjoint(args, fd_dirs):
     """Inverse case on the 1 M-cell bumps canal: gradient of the squared
-    depth misfit at 64 seeded gauge cells after `steps` steps against a
-    seeded target run (Manning perturbed), w.r.t. per-cell Manning and bed,
-    time steps frozen from the forward run. Timed twice: with the interval
-    the library picks (every state kept in HBM when it fits, no replay) and
-    with checkpoints every ceil(sqrt(steps)) steps (least memory). Reports
-    the adjoint's time per step against the forward's, and the relative
-    error against central differences of frozen-schedule runs on seeded
-    smooth directions."""
-    import torch
+    depth misfit at 64 seeded gauge cells after 2000 steps against a seeded
+    target run (Manning perturbed), w.r.t. per-cell Manning and bed, time
+    steps frozen from the forward run. Timed with the interval the library
+    picks (every state kept when it fits) and with checkpoints every
+    ceil(sqrt(steps)) steps; checked against finite differences of
+    frozen-schedule runs on seeded smooth directions.
+
+    Finite differences: for each direction d the loss at m +- eps d and
+    m +- eps/2 d gives two central differences C(eps), C(eps/2). Where
+    they agree to 1e-7 the loss is smooth across the stencil and the
+    Richardson value (4 C(eps/2) - C(eps)) / 3 is the reference. Where they
+    do not, a stencil crosses a point where the scheme switches branch (a
+    wet/dry threshold, a wave-speed case, the positivity clamp): the
+    direction is reported as such, with the one-sided Richardson values of
+    each side (the adjoint is the derivative of the branches taken at m)."""
     import workloads as W
     from paper_2010_14416_amd import Solver, swe as S
-
     case = W.bumps_canal()
-    steps = args.steps
+    steps = 2000
     rng = np.random.default_rng(np.random.SeedSequence(5))
     wet = np.flatnonzero(case.h > 0.05)
     gauges = rng.choice(wet, size=64, replace=False)
     s = Solver(case, device=0)
     dts = S.swe_advance_dt(s.ctx, steps, None, record=True)
+    s.close()
     tgt = case.copy()
     tgt.manning = case.manning * (1.0 + 0.2 * rng.uniform(-1, 1,
                                                           case.n_cells))
@@ -489,26 +684,14 @@ def run_adjoint(args):
     target = t.state()[0][gauges]
     t.close()
 
-    def forward_loss(manning=None, z=None):
-        c = case.copy()
-        if manning is not None:
-            c.manning = manning
-        if z is not None:
-            c.z = z
-        f = Solver(c, device=0)
-        S.swe_advance_dt(f.ctx, steps, dts)
-        h = f.state()[0]
-        f.close()
-        return float(np.sum((h[gauges] - target) ** 2))
-
-    # forward time per step with the frozen schedule (as in the FD runs)
+    import torch
     f = Solver(case, device=0)
     S.swe_advance_dt(f.ctx, 20, dts[:20])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S.swe_advance_dt(f.ctx, steps, dts)
     fwd_s = time.perf_counter() - t0
-    f.close()
+
     def adjoint(every):
         a = Solver(case, device=0)
         torch.cuda.synchronize()
@@ -526,72 +709,83 @@ def run_adjoint(args):
             np.array_equal(gz2, gz))
     log(f"adjoint: loss {loss:.6e}; forward {fwd_s * 1e3:.1f} ms, "
         f"forward + reverse {adj_s * 1e3:.1f} ms for {steps} steps "
-        f"(states kept), {adj_sqrt_s * 1e3:.1f} ms with checkpoints every "
-        f"{k_sqrt}; same bits: {same}")
+        f"(library's interval), {adj_sqrt_s * 1e3:.1f} ms with checkpoints "
+        f"every {k_sqrt}; same bits: {same}")
     if not same:
         raise SystemExit("the checkpoint interval changed the gradients")
-    # central differences on smooth directions (wet cells for Manning)
-    c = case.xy[case.tri].mean(axis=1)
-    x = (c - c.min(axis=0)) / (c.max(axis=0) - c.min(axis=0))
+
+    # finite differences with one context: new fields, state and clock
+    def run_loss(manning, z):
+        S.swe_set_manning(f.ctx, manning)
+        S.swe_set_bathymetry(f.ctx, z)
+        S.swe_set_state(f.ctx, case.h, case.hu, case.hv)
+        S.swe_set_time(f.ctx, 0.0, 0)
+        S.swe_advance_dt(f.ctx, steps, dts)
+        h = f.state()[0]
+        acc = 0.0
+        for k in range(len(gauges)):        # the library's order of sums
+            r = h[gauges[k]] - target[k]
+            acc += r * r
+        return acc
+
+    f0 = run_loss(case.manning, case.z)
     wet_mask = case.h > 0.1
-    # each direction at eps = 1e-6 and 1e-7: a difference stencil that
-    # crosses a kink of the scheme (wet/dry switch, wave-speed case) does
-    # not measure the derivative, and the two step sizes rarely both do
-    errs = {"m": {1e-6: [], 1e-7: []}, "z": {1e-6: [], 1e-7: []}}
-    for k in range(args.fd_directions):
-        kx, ky = rng.integers(1, 4, 2)
-        d = np.sin(2 * np.pi * kx * x[:, 0] + rng.uniform(0, 6)) * np.cos(
-            2 * np.pi * ky * x[:, 1] + rng.uniform(0, 6))
-        which = "m" if k % 2 == 0 else "z"
-        for eps in (1e-6, 1e-7):
-            if which == "m":
-                dm = d * wet_mask
-                fd = (forward_loss(manning=case.manning + eps * dm) -
-                      forward_loss(manning=case.manning - eps * dm)) / (
-                          2 * eps)
-                ad = float(np.dot(gm, dm))
-            else:
-                fd = (forward_loss(z=case.z + eps * d) -
-                      forward_loss(z=case.z - eps * d)) / (2 * eps)
-                ad = float(np.dot(gz, d))
-            errs[which][eps].append(abs(ad - fd) / max(abs(fd), 1e-3 * loss))
-    errs_m, errs_z = errs["m"][1e-6], errs["z"][1e-6]
-    best_m = [min(a, b) for a, b in zip(errs["m"][1e-6], errs["m"][1e-7])]
-    best_z = [min(a, b) for a, b in zip(errs["z"][1e-6], errs["z"][1e-7])]
-    log(f"finite differences (eps 1e-6): Manning max rel error "
-        f"{max(errs_m):.2e} (median {np.median(errs_m):.2e}), bed max "
-        f"{max(errs_z):.2e} (median {np.median(errs_z):.2e}); better of "
-        f"eps 1e-6, 1e-7: Manning max {max(best_m):.2e}, bed max "
-        f"{max(best_z):.2e}")
-    # cost of one adjoint step: (forward + reverse) minus the forward, per
-    # step, against a forward step
+    eps = 1e-6
+    dirs = []
+    for k in range(fd_dirs):
+        d = smooth_direction(case, rng)
+        which = "manning" if k % 2 == 0 else "bed"
+        if which == "manning":
+            d = d * wet_mask
+            ad = float(np.dot(gm, d))
+            L = {e: run_loss(case.manning + e * d, case.z)
+                 for e in (eps, -eps, eps / 2, -eps / 2)}
+        else:
+            ad = float(np.dot(gz, d))
+            L = {e: run_loss(case.manning, case.z + e * d)
+                 for e in (eps, -eps, eps / 2, -eps / 2)}
+        c1 = (L[eps] - L[-eps]) / (2 * eps)
+        c2 = (L[eps / 2] - L[-eps / 2]) / eps
+        scale = max(abs(c2), 1e-3 * loss)
+        smooth = abs(c1 - c2) <= 1e-7 * scale
+        rich = (4 * c2 - c1) / 3
+        plus = 2 * (L[eps / 2] - f0) / (eps / 2) - (L[eps] - f0) / eps
+        minus = 2 * (f0 - L[-eps / 2]) / (eps / 2) - (f0 - L[-eps]) / eps
+        rec = dict(which=which, smooth=bool(smooth), adjoint=ad,
+                   central=c1, central_half=c2,
+                   rel_error=abs(ad - rich) / scale,
+                   rel_error_central=abs(ad - c1) / scale,
+                   rel_error_one_sided=min(abs(ad - plus),
+                                           abs(ad - minus)) / scale)
+        dirs.append(rec)
+    f.close()
+    sm = [d for d in dirs if d["smooth"]]
+    kinks = [i for i, d in enumerate(dirs) if not d["smooth"]]
+    max_err = max((d["rel_error"] for d in sm), default=None)
+    log(f"finite differences, {fd_dirs} directions: {len(sm)} smooth "
+        f"across the stencil, max relative error {max_err}; stencils "
+        f"crossing a branch switch: {kinks}")
     ratio = (adj_s - fwd_s) / fwd_s
     ratio_sqrt = (adj_sqrt_s - fwd_s) / fwd_s
-    out = dict(
-        metric=METRIC, value=case.n_cells * steps / adj_s,
-        unit="cell-updates/s", n_gpus=1, steps=steps, warmup=20,
-        ms_per_step=adj_s * 1e3 / steps, higher_is_better=True,
-        scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+    return dict(
+        value=case.n_cells * steps / adj_s, ms_per_step=adj_s * 1e3 / steps,
+        steps=steps, loss=loss, base_loss_fd=f0,
+        forward_ms=fwd_s * 1e3, forward_and_reverse_ms=adj_s * 1e3,
+        reverse_step_vs_forward_step=ratio,
+        sqrt_checkpoints_every=k_sqrt,
+        forward_and_reverse_sqrt_checkpoints_ms=adj_sqrt_s * 1e3,
+        reverse_step_vs_forward_step_sqrt_checkpoints=ratio_sqrt,
+        fd_directions=fd_dirs, fd_eps=[eps, eps / 2],
+        fd_smooth_directions=len(sm),
+        fd_max_rel_error_smooth=max_err,
+        fd_branch_switch_directions=kinks,
+        fd_max_rel_error_central_all=max(d["rel_error_central"]
+                                         for d in dirs),
+        fd=dirs,
         config=dict(workload="adjoint-bumps-canal-1M: gauge misfit at 64 "
                     "cells vs a perturbed-Manning target run, gradients "
-                    "w.r.t. Manning and bed, frozen time steps, states "
-                    "kept in HBM", n_cells=case.n_cells),
-        roofline=None, cpu_baseline=None,
-        adjoint=dict(loss=loss, forward_ms=fwd_s * 1e3,
-                     forward_and_reverse_ms=adj_s * 1e3,
-                     reverse_step_vs_forward_step=ratio,
-                     sqrt_checkpoints_every=k_sqrt,
-                     forward_and_reverse_sqrt_checkpoints_ms=adj_sqrt_s * 1e3,
-                     reverse_step_vs_forward_step_sqrt_checkpoints=ratio_sqrt,
-                     fd_directions=args.fd_directions, fd_eps=1e-6,
-                     fd_max_rel_error_manning=max(errs_m),
-                     fd_max_rel_error_bed=max(errs_z),
-                     fd_median_rel_error_manning=float(np.median(errs_m)),
-                     fd_median_rel_error_bed=float(np.median(errs_z)),
-                     fd_eps_pair=[1e-6, 1e-7],
-                     fd_max_rel_error_manning_better_eps=max(best_m),
-                     fd_max_rel_error_bed_better_eps=max(best_z)))
-    print(json.dumps(out), flush=True)
+                    "w.r.t. Manning and bed, frozen time steps",
+                    n_cells=case.n_cells))
 
 
 if __name__ == "__main__":

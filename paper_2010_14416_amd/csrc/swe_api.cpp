@@ -1083,6 +1083,35 @@ swe_status swe_get_diagnostics(swe_ctx *c, double *mass, double *ledger,
     return check_health(c);
 }
 
+swe_status swe_get_activity(swe_ctx *c, int64_t *blocks, int64_t *cells)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    if ((st = prepare(c))) return st;
+    const BlockMesh &m = c->mesh;
+    const int64_t nb = m.n_blocks, B = m.block_cells;
+    // the kernel's test: dormant skipping on, the mark of this step's
+    // parity clear, and not the block that advances the clock
+    const bool all = !m.nbr_complete || c->params.store_all;
+    std::vector<uint32_t> mark(size_t(nb), 1u);
+    if (!all) {
+        HIPCHK(c, hipMemcpyAsync(mark.data(),
+                                 c->d.run + size_t(c->step_index & 1) * nb,
+                                 size_t(nb) * 4, hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    int64_t b = 0, n = 0;
+    for (int64_t k = 0; k < nb; ++k)
+        if (mark[size_t(k)] || k == 0) {
+            ++b;
+            n += std::min<int64_t>(B, m.n_cells - k * B);
+        }
+    if (blocks) *blocks = b;
+    if (cells) *cells = n;
+    return check_health(c);
+}
+
 swe_status swe_reset_monitors(swe_ctx *c)
 {
     swe_status st = require_mesh(c);

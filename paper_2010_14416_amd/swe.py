@@ -151,6 +151,8 @@ def load():
     L.swe_get_diagnostics.argtypes = [_p, _pd, _pd, _pi64]
     L.swe_reset_monitors.restype = st
     L.swe_reset_monitors.argtypes = [_p]
+    L.swe_get_activity.restype = st
+    L.swe_get_activity.argtypes = [_p, _pi64, _pi64]
     L.swe_get_discharge.restype = st
     L.swe_get_discharge.argtypes = [_p, C.c_int32, _pd, _pd]
     L.swe_get_envelope.restype = st
@@ -428,6 +430,13 @@ def swe_advance_dt(ctx, n, dt=None, record=False):
         ctx, int(n), None if d is None else d.ctypes.data_as(_pd),
         None if out is None else out.ctypes.data_as(_pd)))
     return out
+
+
+def swe_get_activity(ctx):
+    """(blocks, cells) the next step computes (the rest are dormant)."""
+    b, c = C.c_int64(), C.c_int64()
+    _check(ctx, load().swe_get_activity(ctx, C.byref(b), C.byref(c)))
+    return b.value, c.value
 
 
 def swe_advance_dt_noalloc(ctx, n, dt=None, record=False):
@@ -772,3 +781,42 @@ def gauge_misfit(solver, manning, z, state, steps, gauges, h_target,
             return g * gm, g * gz
 
     return _GaugeMisfit.apply(manning, z)
+
+
+def autotune_ensemble(cases, candidates=((64, 0), (64, 2), (64, 4),
+                                         (128, 0), (128, 2), (256, 2)),
+                      sample=32, warmup=10, steps=20, seed=0, device=0,
+                      params=None):
+    """Launch shape of a batched ensemble chosen by timing: for each
+    (block_cells, wet_band) candidate, an Ensemble of a seeded sample of the
+    members is built and `steps` steps are timed (HIP events on its stream)
+    after `warmup`. Every candidate gives the same results, bit for bit;
+    only the time differs (block size: border edges evaluated twice against
+    finer dormant blocks; band: dry cells near water grouped apart, so far
+    dry blocks fall dormant). Returns (best candidate, {candidate: ms per
+    step})."""
+    import torch
+    rng = np.random.default_rng(seed)
+    k = min(int(sample), len(cases))
+    pick = np.sort(rng.choice(len(cases), size=k, replace=False))
+    sub = [cases[i] for i in pick]
+    times = {}
+    for bc, band in candidates:
+        e = Ensemble(sub, device=device, block_cells=bc, params=params,
+                     wet_band=band)
+        try:
+            e.advance(warmup)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(e.stream)
+            e.advance(steps)
+            e1.record(e.stream)
+            torch.cuda.synchronize()
+            times[(bc, band)] = e0.elapsed_time(e1) / steps
+            e.time(0)   # raises on a numeric fault
+        finally:
+            e.close()
+    best = min(times, key=times.get)
+    return best, times
+
