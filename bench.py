@@ -98,11 +98,13 @@ def ev_time(stream, fn):
     return e0.elapsed_time(e1)
 
 
-def copy_bandwidth(mb, reps=5):
+def copy_bandwidth(mb, min_ms=200.0):
     """Reference streaming kernel of known traffic: an elementwise pass that
     reads `mb` MiB of float64 and writes `mb` MiB (b = -a, torch's neg
-    kernel; a plain copy may be routed to a DMA engine instead of a kernel).
-    Returns GB/s counting read + write bytes."""
+    kernel; a plain copy may be routed to a DMA engine instead of a kernel),
+    repeated back to back for at least `min_ms` (which also brings the GPU
+    out of the low-clock state of the host-side set-up before the timed
+    steps). Returns GB/s counting read + write bytes."""
     import torch
     n = mb * (1 << 20) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -111,14 +113,17 @@ def copy_bandwidth(mb, reps=5):
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        torch.neg(a, out=b)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    total_ms, reps = 0.0, 0
+    while total_ms < min_ms:
+        e0.record()
+        for _ in range(10):
+            torch.neg(a, out=b)
+        e1.record()
+        torch.cuda.synchronize()
+        total_ms += e0.elapsed_time(e1)
+        reps += 10
     del a, b
-    return 2 * n * 8 / (ms * 1e-3) / 1e9
+    return 2 * n * 8 * reps / (total_ms * 1e-3) / 1e9
 
 
 def cpu_model():
@@ -436,7 +441,10 @@ def run_main(args):
     every_ms = None
     if not args.no_every_block:
         s = solver(store_all=1)
-        s.advance(1 + args.warmup, want_time=True)
+        s.advance(1, want_time=True)
+        if args.copy_mb > 0:
+            copy_bandwidth(args.copy_mb, 100.0)   # out of the set-up's idle
+        s.advance(args.warmup, want_time=True)
         every_ms = ev_time(s.stream, lambda: s.advance(args.steps)) / \
             args.steps
         s.time()

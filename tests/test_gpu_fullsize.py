@@ -4,7 +4,10 @@ times (block_cells 256, Hilbert order, torch stream and workspace).
 * 1 000 000-cell bumps canal: one step and the full 2 000-step run against
   the oracle, every cell.
 * 13 M-cell river: one step against the oracle, every cell; the full
-  1 000-step run against the oracle's run at 4 000 seeded cells
+  1 000-step run against the oracle's own run, every cell, after every
+  100 steps (ten tests in a row, each about half a minute of oracle work
+  on 16 host threads), and against the stored record of that run at 4 000
+  seeded cells
   (tests/golden/river13M_1000steps.json, written by
   tests/golden/make_river_golden.py, which calls only the oracle), plus
   properties that hold at any size.
@@ -149,3 +152,35 @@ def test_river_13M_full_run(river):
     assert abs(t_end - gold["t"]) <= 1e-12 * gold["t"]
     m, led, _ = s.diagnostics()
     assert abs(m - gold["mass"]) <= 1e-12 * gold["mass"]
+
+
+@pytest.fixture(scope="module")
+def river_parts():
+    return {"done": None}
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("part", range(10))
+def test_river_13M_full_run_every_cell(river, river_parts, part):
+    """The headline configuration as bench.py runs it, every cell against
+    the oracle after steps 100, 200, ..., 1000 of the run (one part of 100
+    steps per test, in order)."""
+    case, s, o = river
+    if part == 0:
+        _restart(case, s, o)
+        river_parts["done"] = 0
+    assert river_parts["done"] == 100 * part, "parts run in order"
+    t0 = time.time()
+    s.advance(100)
+    n_ora, t_ora = o.run(100)
+    t_gpu, _, steps = s.time()
+    say(f"  steps {100 * part + 1}..{100 * (part + 1)}: oracle "
+        f"{time.time() - t0:.0f} s")
+    assert n_ora == 100 and steps == 100 * (part + 1)
+    assert abs(t_gpu - t_ora) <= 1e-12 * t_ora
+    for k, a, b in zip(("h", "hu", "hv"), s.state(), o.state()):
+        err = rel_linf(a, b)
+        say(f"  all {case.n_cells} cells: rel Linf {k} = {err:.3e}")
+        assert err <= 1e-9
+    river_parts["done"] = 100 * (part + 1)
+
