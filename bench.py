@@ -184,20 +184,23 @@ def cpu_baseline(case, seconds, threads, samples=3, single_steps=10):
 
 def _read_counter_csv(path, counter):
     """Per-dispatch values of one counter from a rocprofv3 counter-collection
-    CSV: {kernel name: [KiB per dispatch, ...]}."""
+    CSV, in dispatch order: {kernel name: [value per dispatch, ...]}."""
     import csv
-    out = {}
+    rows = []
     with open(path, newline="") as f:
         for row in csv.DictReader(f):
             if row.get("Counter_Name", counter) != counter:
                 continue
-            out.setdefault(row["Kernel_Name"], []).append(
-                float(row["Counter_Value"]))
+            rows.append((int(row.get("Dispatch_Id") or len(rows)),
+                         row["Kernel_Name"], float(row["Counter_Value"])))
+    out = {}
+    for _, name, v in sorted(rows):
+        out.setdefault(name, []).append(v)
     return out
 
 
 def pmc_summary(fetch_csv, write_csv, copy_mb, n_cells, out_path,
-                valu_csv=None, steps=""):
+                valu_csv=None, steps="", select=""):
     """Per-launch HBM traffic of the step kernel from two rocprofv3 --pmc
     runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by the
     ratio of known to counted bytes of the reference streaming kernel; with
@@ -205,7 +208,9 @@ def pmc_summary(fetch_csv, write_csv, copy_mb, n_cells, out_path,
     SQ_INSTS_VALU_TRANS_F64, SQ_BUSY_CU_CYCLES): instructions per launch and
     the share of the kernel's cycles a SIMD spends issuing them (4 cycles
     per wave64 instruction, 16 for the quarter-rate FP64 transcendentals,
-    1 024 SIMDs; SQ_BUSY_CU_CYCLES summed over the 256 CUs)."""
+    1 024 SIMDs; SQ_BUSY_CU_CYCLES summed over the 256 CUs). `select`
+    ("lo:hi") keeps only those dispatches of the step kernel (in dispatch
+    order), e.g. the timed steps of the run."""
     fetch = _read_counter_csv(fetch_csv, "FETCH_SIZE")
     write = _read_counter_csv(write_csv, "WRITE_SIZE")
 
@@ -216,6 +221,9 @@ def pmc_summary(fetch_csv, write_csv, copy_mb, n_cells, out_path,
         if not ks:
             raise SystemExit(f"no dispatch of a kernel matching {key!r}")
         vals = [v for k in ks for v in d[k]]
+        if select and key == "swe_step_kernel":
+            lo, hi = (int(x) for x in select.split(":"))
+            vals = vals[lo:hi]
         return sum(vals) / len(vals), len(vals)
 
     known = copy_mb * (1 << 20)
@@ -225,7 +233,7 @@ def pmc_summary(fetch_csv, write_csv, copy_mb, n_cells, out_path,
     f_kib, nf = pick(fetch, "swe_step_kernel")
     w_kib, nw = pick(write, "swe_step_kernel")
     res = dict(kernel="swe_step_kernel", kernel_sha256=kernel_hash(),
-               n_cells=n_cells, steps=steps,
+               n_cells=n_cells, steps=steps, dispatches_kept=select,
                fetch_kib_per_launch=f_kib, write_kib_per_launch=w_kib,
                dispatches=dict(fetch=nf, write=nw),
                reference=dict(kernel="torch neg (elementwise, float64)",
@@ -298,6 +306,9 @@ def main():
     ap.add_argument("--pmc-steps", default="",
                     help="with --pmc-summary: which steps the counter runs "
                          "covered (recorded in the summary)")
+    ap.add_argument("--pmc-dispatches", default="",
+                    help="with --pmc-summary: lo:hi, the step-kernel "
+                         "dispatches (in order) to average")
     ap.add_argument("--pmc-out", default=TRAFFIC_FILE)
     ap.add_argument("--pmc-cells", type=int, default=13_004_176,
                     help="cell count of the profiled workload")
@@ -332,7 +343,7 @@ def main():
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_mb,
                     args.pmc_cells, args.pmc_out, args.pmc_valu,
-                    args.pmc_steps)
+                    args.pmc_steps, args.pmc_dispatches)
         return
 
     if args.gpus != 1:
@@ -587,18 +598,18 @@ def leg_ensemble(args, steps, warmup, solo, tune, tune_sample=32,
     n = sum(c.n_cells for c in cases)
     log(f"ensemble: {len(cases)} members, {n} cells "
         f"({time.perf_counter() - t0:.1f} s to generate)")
-    best, table = (64, 2), {}
+    best, table = (64, 2, 0), {}
     if tune:
         t0 = time.perf_counter()
         best, table = S.autotune_ensemble(cases, sample=tune_sample,
                                           warmup=5, steps=tune_steps)
         log(f"autotuner ({time.perf_counter() - t0:.1f} s): "
-            + ", ".join(f"{bc}/{b}: {ms:.4f} ms" for (bc, b), ms in
+            + ", ".join(f"{bc}/{b}/{t}: {ms:.4f} ms" for (bc, b, t), ms in
                         sorted(table.items())) + f"; best {best}")
     t1 = time.perf_counter()
     ens = Ensemble(cases, block_cells=best[0], wet_band=best[1],
                    group_wet=not args.no_group_wet,
-                   params={"block_threads": args.block_threads})
+                   params={"block_threads": best[2]})
     ens.advance(warmup)
     ens.time(0)
     setup_s = time.perf_counter() - t1
@@ -628,8 +639,9 @@ def leg_ensemble(args, steps, warmup, solo, tune, tune_sample=32,
     return dict(
         value=value, members=len(cases), n_cells=n, steps=steps,
         ensemble_ms=ens_ms, ms_per_step=ms_per_step,
-        block_cells=best[0], wet_band=best[1],
-        autotune={f"{bc}x{b}": ms for (bc, b), ms in table.items()},
+        block_cells=best[0], wet_band=best[1], block_threads=best[2],
+        autotune={f"cells {bc} band {b} threads {t or bc}": ms
+                  for (bc, b, t), ms in table.items()},
         autotune_sample=tune_sample if tune else 0,
         one_at_a_time_ms_per_member=per[0],
         one_at_a_time_ms_per_member_graph=per[96],
@@ -666,14 +678,17 @@ def leg_adjoint(args, fd_dirs):
     ceil(sqrt(steps)) steps; checked against finite differences of
     frozen-schedule runs on seeded smooth directions.
 
-    Finite differences: for each direction d the loss at m +- eps d and
-    m +- eps/2 d gives two central differences C(eps), C(eps/2). Where
-    they agree to 1e-7 the loss is smooth across the stencil and the
-    Richardson value (4 C(eps/2) - C(eps)) / 3 is the reference. Where they
-    do not, a stencil crosses a point where the scheme switches branch (a
-    wet/dry threshold, a wave-speed case, the positivity clamp): the
-    direction is reported as such, with the one-sided Richardson values of
-    each side (the adjoint is the derivative of the branches taken at m)."""
+    Finite differences: for each direction d the loss at m + t d for
+    t = +-eps, +-eps/2, +-eps/4. On each side the one-sided Richardson
+    values at (eps, eps/2) and (eps/2, eps/4) agree where the loss is
+    smooth on that side; a branch switch of the scheme inside the stencil
+    (a wet/dry threshold, a wave-speed case, the positivity clamp, the
+    reconstruction's max) breaks the agreement. Both sides smooth and
+    equal: the central Richardson value (4 C(eps/2) - C(eps)) / 3 is the
+    reference; one side smooth: that side's value (the adjoint is the
+    derivative of the branches taken at m, so it equals the one-sided
+    derivative on a side without a switch); neither: the direction is
+    reported and not checked."""
     import workloads as W
     from paper_2010_14416_amd import Solver, swe as S
     case = W.bumps_canal()
@@ -746,33 +761,51 @@ def leg_adjoint(args, fd_dirs):
         if which == "manning":
             d = d * wet_mask
             ad = float(np.dot(gm, d))
-            L = {e: run_loss(case.manning + e * d, case.z)
-                 for e in (eps, -eps, eps / 2, -eps / 2)}
+            L = {t: run_loss(case.manning + t * d, case.z)
+                 for t in (eps, -eps, eps / 2, -eps / 2, eps / 4, -eps / 4)}
         else:
             ad = float(np.dot(gz, d))
-            L = {e: run_loss(case.manning, case.z + e * d)
-                 for e in (eps, -eps, eps / 2, -eps / 2)}
+            L = {t: run_loss(case.manning, case.z + t * d)
+                 for t in (eps, -eps, eps / 2, -eps / 2, eps / 4, -eps / 4)}
+        scale = max(abs(ad), 1e-3 * loss)
         c1 = (L[eps] - L[-eps]) / (2 * eps)
         c2 = (L[eps / 2] - L[-eps / 2]) / eps
-        scale = max(abs(c2), 1e-3 * loss)
-        smooth = abs(c1 - c2) <= 1e-7 * scale
-        rich = (4 * c2 - c1) / 3
-        plus = 2 * (L[eps / 2] - f0) / (eps / 2) - (L[eps] - f0) / eps
-        minus = 2 * (f0 - L[-eps / 2]) / (eps / 2) - (f0 - L[-eps]) / eps
-        rec = dict(which=which, smooth=bool(smooth), adjoint=ad,
-                   central=c1, central_half=c2,
-                   rel_error=abs(ad - rich) / scale,
-                   rel_error_central=abs(ad - c1) / scale,
-                   rel_error_one_sided=min(abs(ad - plus),
-                                           abs(ad - minus)) / scale)
-        dirs.append(rec)
+        # one-sided Richardson values per side, at (eps, eps/2) and
+        # (eps/2, eps/4); a side is smooth when they agree
+        sides = {}
+        for sgn, name in ((1.0, "plus"), (-1.0, "minus")):
+            q = [(L[sgn * h] - f0) / (sgn * h) for h in (eps, eps / 2,
+                                                         eps / 4)]
+            r1, r2 = 2 * q[1] - q[0], 2 * q[2] - q[1]
+            sides[name] = dict(value=r2, smooth=abs(r1 - r2) <= 1e-7 * scale)
+        smooth_both = (sides["plus"]["smooth"] and sides["minus"]["smooth"]
+                       and abs(sides["plus"]["value"] -
+                               sides["minus"]["value"]) <= 1e-7 * scale)
+        if smooth_both:
+            kind = "smooth"
+            ref = [(4 * c2 - c1) / 3]
+        else:
+            ref = [v["value"] for v in sides.values() if v["smooth"]]
+            kind = "branch switch on one side" if ref else \
+                "branch switches on both sides"
+        dirs.append(dict(
+            which=which, kind=kind, adjoint=ad, central=c1,
+            one_sided_plus=sides["plus"]["value"],
+            one_sided_minus=sides["minus"]["value"],
+            rel_error=(min(abs(ad - v) for v in ref) / scale
+                       if ref else None),
+            rel_error_central=abs(ad - c1) / scale))
     f.close()
-    sm = [d for d in dirs if d["smooth"]]
-    kinks = [i for i, d in enumerate(dirs) if not d["smooth"]]
-    max_err = max((d["rel_error"] for d in sm), default=None)
-    log(f"finite differences, {fd_dirs} directions: {len(sm)} smooth "
-        f"across the stencil, max relative error {max_err}; stencils "
-        f"crossing a branch switch: {kinks}")
+    checked = [d for d in dirs if d["rel_error"] is not None]
+    unchecked = [i for i, d in enumerate(dirs) if d["rel_error"] is None]
+    max_err = max((d["rel_error"] for d in checked), default=None)
+    log(f"finite differences, {fd_dirs} directions: "
+        f"{sum(d['kind'] == 'smooth' for d in dirs)} smooth, "
+        f"{sum(d['kind'] == 'branch switch on one side' for d in dirs)} "
+        f"with a branch switch on one side; max relative error over the "
+        f"{len(checked)} checked {max_err}; branch switches on both sides "
+        f"(not checked): {unchecked}; central differences alone: max "
+        f"{max(d['rel_error_central'] for d in dirs):.2e}")
     ratio = (adj_s - fwd_s) / fwd_s
     ratio_sqrt = (adj_sqrt_s - fwd_s) / fwd_s
     return dict(
@@ -783,10 +816,10 @@ def leg_adjoint(args, fd_dirs):
         sqrt_checkpoints_every=k_sqrt,
         forward_and_reverse_sqrt_checkpoints_ms=adj_sqrt_s * 1e3,
         reverse_step_vs_forward_step_sqrt_checkpoints=ratio_sqrt,
-        fd_directions=fd_dirs, fd_eps=[eps, eps / 2],
-        fd_smooth_directions=len(sm),
-        fd_max_rel_error_smooth=max_err,
-        fd_branch_switch_directions=kinks,
+        fd_directions=fd_dirs, fd_eps=[eps, eps / 2, eps / 4],
+        fd_checked_directions=len(checked),
+        fd_max_rel_error=max_err,
+        fd_unchecked_directions=unchecked,
         fd_max_rel_error_central_all=max(d["rel_error_central"]
                                          for d in dirs),
         fd=dirs,

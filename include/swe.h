@@ -79,7 +79,9 @@ typedef struct {
     int32_t reorder;       /* 1: space-filling-curve cell order (default);
                               0: keep the user order; next set_mesh           */
     int32_t block_threads; /* threads per block: block_cells, 2*block_cells,
-                              or 0 = automatic (= block_cells) (0)            */
+                              or 0 = automatic: block_cells, and
+                              2*block_cells on a mesh of fewer than 256
+                              blocks (latency-bound) (0)                     */
     int32_t load_schedule; /* 0: edge and cell geometry read only where it
                               can change the result (not between cells
                               holding no water) (default); 1: all geometry

@@ -786,6 +786,18 @@ swe_status swe_get_time(swe_ctx *c, double *t, double *last_dt,
 
 namespace swe {
 
+// Threads per block of the step: block_threads, or with 0 one per cell,
+// two per cell on a mesh of fewer blocks than the GPU has compute units,
+// whose step is bound by each block's chain of dependent loads and
+// arithmetic rather than by throughput (the 4 000-cell canal: 9.5 -> 8.7 us
+// per step); the results are the same bits either way.
+int step_threads(const swe_ctx *c)
+{
+    if (c->params.block_threads != 0) return c->params.block_threads;
+    const int B = c->mesh.block_cells;
+    return c->mesh.n_blocks < 256 && B <= 512 ? 2 * B : B;
+}
+
 swe_status ctx_prepare(swe_ctx *c) { return prepare(c); }
 
 swe_status ctx_fail(swe_ctx *c, swe_status st, const std::string &msg)
@@ -852,9 +864,7 @@ swe_status ctx_step_between(swe_ctx *c, const double *const in[3],
     a.mon = nullptr;
     a.cur = c->cur_slot;
     a.step_index = c->step_index;
-    const int threads = c->params.block_threads == 0
-                            ? c->mesh.block_cells
-                            : c->params.block_threads;
+    const int threads = step_threads(c);
     hipError_t e = launch_step(a, c->mesh.block_cells, threads,
                                c->params.load_schedule, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
@@ -887,9 +897,7 @@ swe_status ctx_enqueue(swe_ctx *c, StepArgs &a, int64_t n,
 {
     const BlockMesh &m = c->mesh;
     const size_t nc = size_t(m.n_cells);
-    const int threads = c->params.block_threads == 0
-                            ? m.block_cells
-                            : c->params.block_threads;
+    const int threads = step_threads(c);
     if (!dt_fixed && !dt_log && !slots && !run_log && !r_log) {
         // plain steps: one launch each, or graph replays (graph_steps)
         const StepBuffers b{{c->d.h[0], c->d.h[1]},

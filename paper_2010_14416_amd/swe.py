@@ -783,26 +783,31 @@ def gauge_misfit(solver, manning, z, state, steps, gauges, h_target,
     return _GaugeMisfit.apply(manning, z)
 
 
-def autotune_ensemble(cases, candidates=((64, 0), (64, 2), (64, 4),
-                                         (128, 0), (128, 2), (256, 2)),
+def autotune_ensemble(cases, candidates=((64, 0, 0), (64, 2, 0), (64, 4, 0),
+                                         (64, 2, 128), (128, 2, 0),
+                                         (128, 2, 256), (256, 2, 0)),
                       sample=32, warmup=10, steps=20, seed=0, device=0,
                       params=None):
     """Launch shape of a batched ensemble chosen by timing: for each
-    (block_cells, wet_band) candidate, an Ensemble of a seeded sample of the
-    members is built and `steps` steps are timed (HIP events on its stream)
-    after `warmup`. Every candidate gives the same results, bit for bit;
-    only the time differs (block size: border edges evaluated twice against
-    finer dormant blocks; band: dry cells near water grouped apart, so far
-    dry blocks fall dormant). Returns (best candidate, {candidate: ms per
-    step})."""
+    (block_cells, wet_band, block_threads) candidate (block_threads 0: one
+    thread per cell), an Ensemble of a seeded sample of the members is built
+    and `steps` steps are timed (HIP events on its stream) after `warmup`.
+    Every candidate gives the same results, bit for bit; only the time
+    differs (block size: border edges evaluated twice against finer dormant
+    blocks; band: dry cells near water grouped apart, so far dry blocks
+    fall dormant; two threads per cell: shorter edge loops, fewer blocks per
+    compute unit). Returns (best candidate, {candidate: ms per step})."""
     import torch
     rng = np.random.default_rng(seed)
     k = min(int(sample), len(cases))
     pick = np.sort(rng.choice(len(cases), size=k, replace=False))
     sub = [cases[i] for i in pick]
     times = {}
-    for bc, band in candidates:
-        e = Ensemble(sub, device=device, block_cells=bc, params=params,
+    for cand in candidates:
+        bc, band, threads = (tuple(cand) + (0,))[:3]
+        p = dict(params or {})
+        p["block_threads"] = threads
+        e = Ensemble(sub, device=device, block_cells=bc, params=p,
                      wet_band=band)
         try:
             e.advance(warmup)
@@ -813,10 +818,9 @@ def autotune_ensemble(cases, candidates=((64, 0), (64, 2), (64, 4),
             e.advance(steps)
             e1.record(e.stream)
             torch.cuda.synchronize()
-            times[(bc, band)] = e0.elapsed_time(e1) / steps
+            times[(bc, band, threads)] = e0.elapsed_time(e1) / steps
             e.time(0)   # raises on a numeric fault
         finally:
             e.close()
     best = min(times, key=times.get)
     return best, times
-

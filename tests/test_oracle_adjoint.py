@@ -86,8 +86,25 @@ def smooth_directions(case, n, seed):
     return out
 
 
-@pytest.mark.parametrize("which", ["manning", "z"])
-def test_gradients_match_central_differences(which):
+def one_sided_estimates(loss_at, f0, eps):
+    """Derivative estimates of a piecewise smooth loss along a direction
+    from runs at t = +-eps, +-eps/2, +-eps/4: on each side the Richardson
+    values 2 D(h/2) - D(h) of the one-sided quotients D(h) = (L(s h) - f0)
+    / (s h) at h = eps and eps/2. A side is smooth when its two values
+    agree; a branch switch of the scheme (wet/dry threshold, wave-speed
+    case, the reconstruction's max, the positivity clamp) inside the
+    stencil breaks that agreement. Returns [(value, spread)] per side."""
+    out = []
+    for s in (1.0, -1.0):
+        d = [(loss_at(s * h) - f0) / (s * h) for h in (eps, eps / 2, eps / 4)]
+        r1, r2 = 2 * d[1] - d[0], 2 * d[2] - d[1]
+        out.append((r2, abs(r1 - r2)))
+    return out
+
+
+def test_manning_gradient_matches_central_differences():
+    """Manning acts smoothly on wet cells: central differences agree with
+    the adjoint on every seeded direction."""
     case = W.river(n_target=6_000, workers=1)
     gauges, target, dts = misfit_problem(case, 30)
     loss, gm, gz = A.gauge_misfit(case, dts, gauges, target)
@@ -95,26 +112,43 @@ def test_gradients_match_central_differences(which):
     # the misfit is a sum of squared small differences: the relative
     # rounding of the two implementations (cbrt) is amplified
     assert abs(loss - c_loss(case, dts, gauges, target)) <= 1e-9 * loss
-    # Manning acts smoothly on wet cells; the bed also enters the
-    # reconstruction's max and the wet/dry thresholds, whose kinks a
-    # finite-difference stencil crosses now and then: the bed takes the
-    # better of two step sizes and a looser bar
     wet = case.h > 0.1
+    eps = 1e-6
     for d in smooth_directions(case, 4, seed=7):
-        errs = []
-        for eps in ((1e-6,) if which == "manning" else (1e-6, 1e-7)):
-            if which == "manning":
-                args_p = dict(m=case.manning + eps * d * wet)
-                args_m = dict(m=case.manning - eps * d * wet)
-                dd = float(np.dot(gm, d * wet))
-            else:
-                args_p = dict(z=case.z + eps * d)
-                args_m = dict(z=case.z - eps * d)
-                dd = float(np.dot(gz, d))
-            fd = (c_loss(case, dts, gauges, target, **args_p) -
-                  c_loss(case, dts, gauges, target, **args_m)) / (2 * eps)
-            errs.append(abs(dd - fd) / max(abs(fd), 1e-3 * loss))
-        assert min(errs) <= (1e-6 if which == "manning" else 1e-5), errs
+        fd = (c_loss(case, dts, gauges, target, m=case.manning + eps * d * wet)
+              - c_loss(case, dts, gauges, target,
+                       m=case.manning - eps * d * wet)) / (2 * eps)
+        ad = float(np.dot(gm, d * wet))
+        assert abs(ad - fd) <= 1e-6 * max(abs(fd), 1e-3 * loss)
+
+
+def test_bed_gradient_matches_one_sided_differences():
+    """The bed also enters the reconstruction's max and the wet/dry
+    thresholds, whose branch switches lie densely around the base state: a
+    central difference straddles one in most directions (and, for a tie at
+    the base state, measures the mean of the two one-sided slopes). The
+    adjoint differentiates the branches taken at the base state, so it
+    must equal the one-sided derivative of a side on which the loss is
+    smooth (two Richardson values agreeing to 1e-7), to 1e-6. Directions
+    with a branch switch within the stencil on both sides are skipped,
+    at most one of four."""
+    case = W.river(n_target=6_000, workers=1)
+    gauges, target, dts = misfit_problem(case, 30)
+    loss, gm, gz = A.gauge_misfit(case, dts, gauges, target)
+    f0 = c_loss(case, dts, gauges, target)
+    checked = 0
+    for d in smooth_directions(case, 4, seed=7):
+        ad = float(np.dot(gz, d))
+        scale = max(abs(ad), 1e-3 * loss)
+        est = one_sided_estimates(
+            lambda t: c_loss(case, dts, gauges, target, z=case.z + t * d),
+            f0, 1e-6)
+        smooth = [v for v, spread in est if spread <= 1e-7 * scale]
+        if not smooth:
+            continue
+        checked += 1
+        assert min(abs(ad - v) for v in smooth) <= 1e-6 * scale, est
+    assert checked >= 3
 
 
 def test_frictionless_canal_has_zero_manning_gradient():
