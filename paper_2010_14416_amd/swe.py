@@ -12,6 +12,7 @@ import ctypes as C
 import math
 import os
 import re
+import time
 
 import numpy as np
 
@@ -787,11 +788,14 @@ def autotune_ensemble(cases, candidates=((64, 0, 0), (64, 2, 0), (64, 4, 0),
                                          (64, 2, 128), (128, 2, 0),
                                          (128, 2, 256), (256, 2, 0)),
                       sample=32, warmup=10, steps=20, seed=0, device=0,
-                      params=None):
+                      params=None, warm_ms=100.0):
     """Launch shape of a batched ensemble chosen by timing: for each
     (block_cells, wet_band, block_threads) candidate (block_threads 0: one
     thread per cell), an Ensemble of a seeded sample of the members is built
-    and `steps` steps are timed (HIP events on its stream) after `warmup`.
+    and `steps` steps are timed (HIP events on its stream) after `warmup`
+    steps and at least `warm_ms` of untimed steps (a GPU just out of the
+    host-side set-up runs the first tens of milliseconds of compute-heavy
+    work slower).
     Every candidate gives the same results, bit for bit; only the time
     differs (block size: border edges evaluated twice against finer dormant
     blocks; band: dry cells near water grouped apart, so far dry blocks
@@ -811,6 +815,11 @@ def autotune_ensemble(cases, candidates=((64, 0, 0), (64, 2, 0), (64, 4, 0),
                      wet_band=band)
         try:
             e.advance(warmup)
+            e.time(0)
+            t0 = time.perf_counter()
+            while (time.perf_counter() - t0) * 1e3 < warm_ms:
+                e.advance(warmup)
+                e.time(0)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()

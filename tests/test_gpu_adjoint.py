@@ -184,7 +184,7 @@ def test_full_size_canal_gradients_and_checkpoints():
     x = (c - c.min(axis=0)) / (c.max(axis=0) - c.min(axis=0))
     wet = case.h > 0.1
     f0 = gpu_loss(case, dts, gauges, target)
-    assert f0 == loss
+    assert abs(f0 - loss) <= 1e-13 * loss   # numpy sums in another order
     for which in ("m", "z"):
         kx, ky = rng.integers(1, 4, 2)
         d = np.sin(2 * np.pi * kx * x[:, 0] + rng.uniform(0, 6)) * np.cos(
