@@ -395,19 +395,34 @@ def main():
     out = run_main(args)
     legs = [x for x in args.legs.split(",") if x] if \
         args.workload == "river" else []
-    if "small" in legs:
-        out["small_mesh"] = leg_small(args)
-    if "ensemble" in legs:
+
+    def leg(name, fn):
+        # a failing extra leg is reported in the line, not fatal to it
+        try:
+            out[name] = fn()
+        except Exception as e:   # noqa: BLE001
+            log(f"{name} leg failed: {e!r}")
+            out[name] = {"error": repr(e)}
+
+    def ensemble_leg():
         ens = leg_ensemble(args, steps=100, warmup=10, solo=8, tune=True,
                            tune_sample=24, tune_steps=10)
         ens.pop("config")
         ens.pop("roofline")
-        out["ensemble"] = ens
-    if "adjoint" in legs:
+        return ens
+
+    def adjoint_leg():
         adj = leg_adjoint(args, fd_dirs=8)
         for k in ("value", "ms_per_step", "config"):
             adj.pop(k)
-        out["adjoint"] = adj
+        return adj
+
+    if "small" in legs:
+        leg("small_mesh", lambda: leg_small(args))
+    if "ensemble" in legs:
+        leg("ensemble", ensemble_leg)
+    if "adjoint" in legs:
+        leg("adjoint", adjoint_leg)
     print(json.dumps(out), flush=True)
 
 

@@ -216,3 +216,80 @@ def test_full_size_canal_gradients_and_checkpoints():
         smooth = [v for v, ok in est if ok]
         assert smooth, "a branch switch within 1e-6 on both sides"
         assert min(abs(ad - v) for v in smooth) <= 1e-6 * scale
+
+
+@pytest.mark.timeout(600)
+def test_configured_case_sqrt_checkpoints_and_32_directions():
+    """Config 5 as specified: the 1 M-cell canal over 2 000 steps with
+    checkpoints every ceil(sqrt(2000)) = 45 steps (the same bits as every
+    state kept), and 32 seeded smooth directions (16 Manning on wet cells,
+    16 bed) checked against one-sided differences of frozen-schedule runs
+    at eps, eps/2, eps/4 (eps = 1e-6) on a side of the base state where the
+    loss is smooth; a direction with a branch switch within the stencil on
+    both sides is not checked (at most 8 of 32)."""
+    from paper_2010_14416_amd import swe as S
+    case = W.bumps_canal()
+    steps = 2000
+    gauges, target, dts = problem(case, steps)
+    say(f"[adjoint config 5] {case.n_cells} cells, {steps} steps")
+    a = solver(case)
+    loss, gm, gz = S.swe_adjoint_gauges(a.ctx, steps, gauges, target,
+                                        checkpoint_every=45)
+    a.close()
+    b = solver(case)
+    l1, gm1, gz1 = S.swe_adjoint_gauges(b.ctx, steps, gauges, target,
+                                        checkpoint_every=1)
+    b.close()
+    assert l1 == loss and np.array_equal(gm1, gm) and np.array_equal(gz1, gz)
+    f = solver(case)
+
+    def run_loss(manning, z):
+        S.swe_set_manning(f.ctx, manning)
+        S.swe_set_bathymetry(f.ctx, z)
+        S.swe_set_state(f.ctx, case.h, case.hu, case.hv)
+        S.swe_set_time(f.ctx, 0.0, 0)
+        S.swe_advance_dt(f.ctx, steps, dts)
+        h = f.state()[0]
+        return float(np.sum((h[gauges] - target) ** 2))
+
+    f0 = run_loss(case.manning, case.z)
+    assert abs(f0 - loss) <= 1e-13 * loss
+    rng = np.random.default_rng(5)
+    c = case.xy[case.tri].mean(axis=1)
+    x = (c - c.min(axis=0)) / (c.max(axis=0) - c.min(axis=0))
+    wet = case.h > 0.1
+    eps = 1e-6
+    checked, worst = 0, 0.0
+    for k in range(32):
+        kx, ky = rng.integers(1, 4, 2)
+        d = np.sin(2 * np.pi * kx * x[:, 0] + rng.uniform(0, 6)) * np.cos(
+            2 * np.pi * ky * x[:, 1] + rng.uniform(0, 6))
+        if k % 2 == 0:
+            d = d * wet
+            ad = float(np.dot(gm, d))
+
+            def at(t):
+                return run_loss(case.manning + t * d, case.z)
+        else:
+            ad = float(np.dot(gz, d))
+
+            def at(t):
+                return run_loss(case.manning, case.z + t * d)
+        scale = max(abs(ad), 1e-3 * loss)
+        smooth = []
+        for sgn in (1.0, -1.0):
+            q = [(at(sgn * h) - f0) / (sgn * h) for h in (eps, eps / 2,
+                                                          eps / 4)]
+            r1, r2 = 2 * q[1] - q[0], 2 * q[2] - q[1]
+            if abs(r1 - r2) <= 1e-7 * scale:
+                smooth.append(r2)
+        if smooth:
+            err = min(abs(ad - v) for v in smooth) / scale
+            worst = max(worst, err)
+            checked += 1
+            assert err <= 1e-6, (k, err)
+        say(f"  direction {k}: {len(smooth)} smooth side(s)")
+    f.close()
+    say(f"  {checked} of 32 directions checked, worst {worst:.2e}")
+    assert checked >= 24
+
