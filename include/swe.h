@@ -340,6 +340,22 @@ swe_status swe_adjoint_gauges(swe_ctx *ctx, int64_t steps, int32_t n_gauges,
 swe_status swe_get_diagnostics(swe_ctx *ctx, double *mass, double *ledger,
                                int64_t *n_wet);
 
+/* Asynchronous copy of the discharge monitors (sec. 5.3.2: the inflow and
+ * outflow rates go to the host while the steps go on). Enqueues, on a
+ * stream of the library's own ordered after every step enqueued so far,
+ * the per-tag sums of rate and volume (summed as swe_get_discharge does:
+ * the same bits) and their copy into out (host, 2 * SWE_MAX_TAG doubles:
+ * out[2 t] = rate of tag t [m^3/s], out[2 t + 1] = volume [m^3]; pinned
+ * host memory makes the copy overlap the steps). Returns at once. Steps
+ * enqueued afterwards wait only for the sums (a few microseconds), not
+ * for the copy, and do not change the values copied. out must stay valid
+ * until swe_discharge_wait reports the copy done. One copy at a time per
+ * context: SWE_ENOTREADY while one is pending, or with monitors off. */
+swe_status swe_discharge_async(swe_ctx *ctx, double *out);
+/* Completion of the pending asynchronous discharge copy: with block != 0
+ * waits for it; else *done (may be NULL) = 1 if it has landed (or none is
+ * pending), 0 if not yet. */
+swe_status swe_discharge_wait(swe_ctx *ctx, int32_t block, int32_t *done);
 /* Discharge monitors and flood envelope (swe_params.monitors = 1), the
  * outflow and inflow rates of a river reach and the maximum-depth map from
  * which flood lines are drawn (sec. 5). Both are reset to the current state

@@ -92,6 +92,9 @@ size_t layout(const BlockMesh &m, char *base, DevBufs *d)
     t.part_mass = (double *)take(kDiagParts * 8);
     t.part_wet = (unsigned long long *)take(kDiagParts * 8);
     t.flag = (unsigned *)take(256);
+    t.tag_ptr = (int32_t *)take((SWE_MAX_TAG + 1) * 4);
+    t.tag_slot = (int32_t *)take(nbnd * 4);
+    t.tag_out = (double *)take(2 * SWE_MAX_TAG * 8);
     if (d) *d = t;
     return off;
 }
@@ -157,6 +160,25 @@ swe_status prepare(swe_ctx *c)
             return st;
         if ((st = upload(c, d.blk_nbr, m.blk_nbr.data(), m.blk_nbr.size())))
             return st;
+        {
+            // boundary slots of each tag, in increasing slot order
+            const std::vector<int32_t> &bt = m.bnd_tag;
+            std::vector<int32_t> ptr(SWE_MAX_TAG + 1, 0), slot(bt.size());
+            for (int32_t t : bt) ++ptr[size_t(t) + 1];
+            for (int k = 0; k < SWE_MAX_TAG; ++k) ptr[k + 1] += ptr[k];
+            std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+            for (size_t k = 0; k < bt.size(); ++k)
+                slot[size_t(fill[size_t(bt[k])]++)] = int32_t(k);
+            c->tag_ptr_host = ptr;
+            c->tag_slot_host = slot;
+            if ((st = upload(c, d.tag_ptr, c->tag_ptr_host.data(),
+                             c->tag_ptr_host.size())))
+                return st;
+            if (!slot.empty() &&
+                (st = upload(c, d.tag_slot, c->tag_slot_host.data(),
+                             slot.size())))
+                return st;
+        }
         c->mon_host = swe::MonPtrs{d.mon_rate, d.mon_vol, d.blk_bnd, d.h_max,
                               d.t_wet};
         if ((st = upload(c, d.mon, &c->mon_host, 1))) return st;
@@ -395,6 +417,13 @@ swe_status swe_create(swe_ctx **out, int device)
 void swe_destroy(swe_ctx *c)
 {
     if (!c) return;
+    if (c->side) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->side);
+        (void)hipEventDestroy(c->ev_step);
+        (void)hipEventDestroy(c->ev_copy);
+        (void)hipStreamDestroy(c->side);
+    }
     if ((c->ws_owned && c->ws) || c->dt_dev) {
         (void)hipSetDevice(c->device);
         if (c->ws_owned && c->ws) (void)hipFree(c->ws);
@@ -1156,6 +1185,60 @@ swe_status swe_get_discharge(swe_ctx *c, int32_t tag, double *rate,
         }
     if (rate) *rate = sr;
     if (volume) *volume = sv;
+    return SWE_OK;
+}
+
+swe_status swe_discharge_async(swe_ctx *c, double *out)
+{
+    swe_status st = require_mesh(c);
+    if (st != SWE_OK) return st;
+    if (!out) return fail(c, SWE_EINVAL, "null output array");
+    if (!c->params.monitors)
+        return fail(c, SWE_ENOTREADY, "monitors are off (swe_params.monitors)");
+    if (c->copy_pending)
+        return fail(c, SWE_ENOTREADY,
+                    "an asynchronous discharge copy is pending "
+                    "(swe_discharge_wait)");
+    if ((st = prepare(c))) return st;
+    if (!c->side) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_step,
+                                          hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_copy,
+                                          hipEventDisableTiming));
+    }
+    // the side stream follows every step enqueued so far; the next steps
+    // wait for its per-tag sums (a few microseconds), not for the copy
+    HIPCHK(c, hipEventRecord(c->ev_step, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_step, 0));
+    HIPCHK(c, swe::launch_discharge_tags(c->d.mon_rate, c->d.mon_vol,
+                                         c->d.tag_ptr, c->d.tag_slot,
+                                         SWE_MAX_TAG, c->d.tag_out, c->side));
+    HIPCHK(c, hipEventRecord(c->ev_step, c->side));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_step, 0));
+    HIPCHK(c, hipMemcpyAsync(out, c->d.tag_out, 2 * SWE_MAX_TAG * 8,
+                             hipMemcpyDeviceToHost, c->side));
+    HIPCHK(c, hipEventRecord(c->ev_copy, c->side));
+    c->copy_pending = true;
+    return SWE_OK;
+}
+
+swe_status swe_discharge_wait(swe_ctx *c, int32_t block, int32_t *done)
+{
+    if (!c) return SWE_EINVAL;
+    if (done) *done = 1;
+    if (!c->copy_pending) return SWE_OK;
+    if (block) {
+        HIPCHK(c, hipEventSynchronize(c->ev_copy));
+    } else {
+        const hipError_t e = hipEventQuery(c->ev_copy);
+        if (e == hipErrorNotReady) {
+            if (done) *done = 0;
+            return SWE_OK;
+        }
+        HIPCHK(c, e);
+    }
+    c->copy_pending = false;
     return SWE_OK;
 }
 

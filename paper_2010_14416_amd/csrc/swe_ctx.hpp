@@ -34,6 +34,11 @@ struct DevBufs {
     double *part_mass;
     unsigned long long *part_wet;
     unsigned *flag;
+    // boundary slots per tag (tag_ptr: SWE_MAX_TAG + 1 offsets into
+    // tag_slot, slots in increasing order) and the per-tag rate and volume
+    // sums of an asynchronous discharge copy (2 x SWE_MAX_TAG)
+    int32_t *tag_ptr, *tag_slot;
+    double *tag_out;
 };
 
 constexpr int kDiagParts = 1024;
@@ -78,6 +83,13 @@ struct swe_ctx {
     double *dt_dev = nullptr;  // time-step schedule (library-allocated)
     int64_t dt_cap = 0;
     swe::StepGraph graph;      // captured step runs (graph_steps > 0)
+    // asynchronous discharge copies: a stream of the library's own (default
+    // priority), an event marking the step they follow, one marking the
+    // copy's end
+    hipStream_t side = nullptr;
+    hipEvent_t ev_step = nullptr, ev_copy = nullptr;
+    bool copy_pending = false;
+    std::vector<int32_t> tag_ptr_host, tag_slot_host;   // upload sources
 };
 
 namespace swe {

@@ -154,6 +154,10 @@ def load():
     L.swe_reset_monitors.argtypes = [_p]
     L.swe_get_activity.restype = st
     L.swe_get_activity.argtypes = [_p, _pi64, _pi64]
+    L.swe_discharge_async.restype = st
+    L.swe_discharge_async.argtypes = [_p, _p]
+    L.swe_discharge_wait.restype = st
+    L.swe_discharge_wait.argtypes = [_p, C.c_int32, C.POINTER(C.c_int32)]
     L.swe_get_discharge.restype = st
     L.swe_get_discharge.argtypes = [_p, C.c_int32, _pd, _pd]
     L.swe_get_envelope.restype = st
@@ -438,6 +442,34 @@ def swe_get_activity(ctx):
     b, c = C.c_int64(), C.c_int64()
     _check(ctx, load().swe_get_activity(ctx, C.byref(b), C.byref(c)))
     return b.value, c.value
+
+
+def swe_discharge_async(ctx, out):
+    """Enqueues the copy of every tag's discharge rate and volume into out
+    (2 * SWE_MAX_TAG float64: a numpy array, or a pinned torch tensor for a
+    copy that overlaps the steps); out must stay alive until
+    swe_discharge_wait returns True."""
+    if _is_torch(out):
+        if out.dtype.itemsize != 8 or out.numel() < 2 * SWE_MAX_TAG or \
+                out.is_cuda or not out.is_contiguous():
+            raise ValueError("need a contiguous host float64 tensor of "
+                             f"{2 * SWE_MAX_TAG} values")
+        ptr = out.data_ptr()
+    else:
+        if out.dtype != np.float64 or out.size < 2 * SWE_MAX_TAG or \
+                not out.flags["C_CONTIGUOUS"]:
+            raise ValueError(f"need a contiguous float64 array of "
+                             f"{2 * SWE_MAX_TAG} values")
+        ptr = out.ctypes.data
+    _check(ctx, load().swe_discharge_async(ctx, ptr))
+
+
+def swe_discharge_wait(ctx, block=True):
+    """True once the pending asynchronous discharge copy has landed."""
+    done = C.c_int32()
+    _check(ctx, load().swe_discharge_wait(ctx, 1 if block else 0,
+                                          C.byref(done)))
+    return bool(done.value)
 
 
 def swe_advance_dt_noalloc(ctx, n, dt=None, record=False):
