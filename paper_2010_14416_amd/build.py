@@ -44,7 +44,8 @@ def build(verbose: bool = True) -> str:
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src in ["swe_kernels.hip", "swe_adjoint.hip", "swe_noalloc.hip"]:
+    for src in ["swe_kernels.hip", "swe_adjoint.hip", "swe_noalloc.hip",
+                "swe_monitor.hip"]:
         obj = os.path.join(BUILD, src + ".o")
         _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

@@ -15,6 +15,7 @@
 #include "swe_ctx.hpp"
 #include "swe_device.hpp"
 #include "swe_mesh.hpp"
+#include "swe_monitor.hpp"
 
 using swe::BcEntry;
 using swe::BlockMesh;

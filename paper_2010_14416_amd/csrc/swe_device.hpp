@@ -140,11 +140,6 @@ hipError_t launch_diag(const double *h, const double *area, int64_t n,
                        unsigned long long *part_wet, int nparts,
                        hipStream_t s);
 hipError_t launch_fill_u32(unsigned *p, unsigned v, int64_t n, hipStream_t s);
-// out[2 t], out[2 t + 1] = sum of rate, vol over tag t's slots
-hipError_t launch_discharge_tags(const double *rate, const double *vol,
-                                 const int32_t *tag_ptr,
-                                 const int32_t *tag_slot, int n_tags,
-                                 double *out, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 // h_max = h; t_wet = t where h > h_dry, else +inf
 hipError_t launch_envelope_reset(const double *h, int64_t n, double h_dry,

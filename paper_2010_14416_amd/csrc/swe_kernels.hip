@@ -546,24 +546,6 @@ void swe_step_kernel(StepArgs a)
     }
 }
 
-// Per-tag sums of the discharge monitors: thread t adds the rate and
-// volume of tag t's boundary slots in increasing slot order (the order of
-// the host-side sums of swe_get_discharge, so the same bits).
-__global__ __launch_bounds__(256) void discharge_tags_kernel(
-    const double *rate, const double *vol, const int32_t *tag_ptr,
-    const int32_t *tag_slot, int n_tags, double *out)
-{
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_tags) return;
-    double r = 0.0, v = 0.0;
-    for (int k = tag_ptr[t]; k < tag_ptr[t + 1]; ++k) {
-        r += rate[tag_slot[k]];
-        v += vol[tag_slot[k]];
-    }
-    out[2 * t] = r;
-    out[2 * t + 1] = v;
-}
-
 __global__ void clock_set_kernel(Clock *c, double t, long long steps,
                                  long long step_index)
 {
@@ -823,17 +805,6 @@ hipError_t launch_step(const StepArgs &a, int block_cells, int threads,
         return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
-    return hipGetLastError();
-}
-
-hipError_t launch_discharge_tags(const double *rate, const double *vol,
-                                 const int32_t *tag_ptr,
-                                 const int32_t *tag_slot, int n_tags,
-                                 double *out, hipStream_t s)
-{
-    hipLaunchKernelGGL(discharge_tags_kernel, dim3((n_tags + 255) / 256),
-                       dim3(256), 0, s, rate, vol, tag_ptr, tag_slot, n_tags,
-                       out);
     return hipGetLastError();
 }
 
