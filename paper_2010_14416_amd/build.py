@@ -29,6 +29,11 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     f"-I{os.path.join(ROOT, 'include')}",
 ]
+# The step kernel without loop strength reduction: its rarely taken loop over
+# edge records past the first NT otherwise carries one address register pair
+# per record array through the Riemann solver, and the kernel no longer fits
+# the registers of six waves per SIMD without spilling.
+HIP_FILE_FLAGS = {"swe_kernels.hip": ["-mllvm", "-disable-lsr"]}
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=off",
               "-fopenmp",
               "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include",
@@ -47,7 +52,8 @@ def build(verbose: bool = True) -> str:
     for src in ["swe_kernels.hip", "swe_adjoint.hip", "swe_noalloc.hip",
                 "swe_monitor.hip"]:
         obj = os.path.join(BUILD, src + ".o")
-        _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        _run([hipcc, *HIP_FLAGS, *HIP_FILE_FLAGS.get(src, []), "-c",
+              os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in ["swe_mesh.cpp", "swe_api.cpp", "swe_ensemble.cpp",
                 "swe_adjoint.cpp", "swe_graph.cpp"]:

@@ -85,7 +85,7 @@ size_t layout(const BlockMesh &m, char *base, DevBufs *d)
     t.mon_rate = (double *)take(nbnd * 8);
     t.mon_vol = (double *)take(nbnd * 8);
     t.blk_bnd = (int32_t *)take(nb * 16);
-    t.blk_nbr = (int32_t *)take(m.blk_nbr.size() * 4);
+    t.act = (unsigned long long *)take(nb * (m.block_cells / 64) * 8);
     t.run = (uint32_t *)take(2 * nb * 4);
     t.h_max = (double *)take(nc * 8);
     t.t_wet = (double *)take(nc * 8);
@@ -159,8 +159,6 @@ swe_status prepare(swe_ctx *c)
             return st;
         if ((st = upload(c, d.blk_bnd, m.blk_bnd.data(), m.blk_bnd.size())))
             return st;
-        if ((st = upload(c, d.blk_nbr, m.blk_nbr.data(), m.blk_nbr.size())))
-            return st;
         {
             // boundary slots of each tag, in increasing slot order
             const std::vector<int32_t> &bt = m.bnd_tag;
@@ -229,6 +227,9 @@ swe_status prepare(swe_ctx *c)
         HIPCHK(c, swe::launch_fill_u32((unsigned *)d.quiet, 0u, m.n_blocks,
                                        c->stream));
         HIPCHK(c, swe::launch_fill_u32(d.run, 1u, 2 * int64_t(m.n_blocks),
+                                       c->stream));
+        HIPCHK(c, swe::launch_fill_u32((unsigned *)d.act, 0u,
+                                       int64_t(m.n_blocks) * m.block_cells / 32,
                                        c->stream));
         c->quiet_dirty = false;
     }
@@ -653,7 +654,6 @@ swe_status swe_mesh_digest(const swe_ctx *c, uint64_t *digest)
     vec(m.be_len);
     vec(m.bnd_tag);
     vec(m.blk_bnd);
-    vec(m.blk_nbr);
     vec(m.tag_length);
     *digest = h;
     return SWE_OK;
@@ -859,9 +859,8 @@ StepArgs ctx_step_args(swe_ctx *c, double t_end)
     a.clock = c->d.clock;
     a.ledger = c->d.ledger;
     a.quiet = c->d.quiet;
-    a.blk_nbr = c->d.blk_nbr;
     a.run = c->d.run;
-    a.skip_dormant = m.nbr_complete ? 1 : 0;
+    a.act = c->d.act;
     a.store_all = c->params.store_all;
     if (c->params.monitors) a.mon = c->d.mon;
     a.g = c->params.g;
@@ -1130,7 +1129,7 @@ swe_status swe_get_activity(swe_ctx *c, int64_t *blocks, int64_t *cells)
     const int64_t nb = m.n_blocks, B = m.block_cells;
     // the kernel's test: dormant skipping on, the mark of this step's
     // parity clear, and not the block that advances the clock
-    const bool all = !m.nbr_complete || c->params.store_all;
+    const bool all = c->params.store_all != 0;
     std::vector<uint32_t> mark(size_t(nb), 1u);
     if (!all) {
         HIPCHK(c, hipMemcpyAsync(mark.data(),

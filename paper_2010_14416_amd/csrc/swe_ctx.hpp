@@ -27,8 +27,8 @@ struct DevBufs {
     int32_t *quiet;
     double *mon_rate, *mon_vol;   // per boundary slot
     int32_t *blk_bnd;             // per block, 4 values
-    int32_t *blk_nbr;             // per block, kNbrSlots neighbour blocks
     uint32_t *run;                // run marks, 2 x n_blocks
+    unsigned long long *act;      // per block, a bit per cell (StepArgs)
     double *h_max, *t_wet;        // per cell (internal order)
     MonPtrs *mon;                 // the five monitor addresses above
     double *part_mass;

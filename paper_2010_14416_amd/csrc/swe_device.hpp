@@ -76,13 +76,14 @@ struct StepArgs {
     double *ledger;           // per block: mass added by the positivity fix
     int32_t *quiet;           // per block: consecutive steps (capped at 2) in
                               // which every cell took the quiet dry path
-    // dormant blocks: per block kNbrSlots neighbour blocks (-1 padded), and
-    // run marks for even and odd step indices (2 x n_blocks); a block runs
-    // at step k if it or a neighbour was not quiet for two steps at step
-    // k - 1, or if skip_dormant is 0
-    const int32_t *blk_nbr;
+    // dormant blocks: run marks for even and odd step indices
+    // (2 x n_blocks), and per block NC / 64 words of bits, one per cell:
+    // the cells not on the quiet dry path in the block's last computed
+    // step. A block runs at step k if it was not quiet for two steps at
+    // step k - 1, or if a cell of another block that shares an edge with
+    // one of its cells was not quiet at step k - 1 or k - 2.
     uint32_t *run;
-    int32_t skip_dormant;
+    unsigned long long *act;
     // monitors, null when off (read at their point of use, so that their
     // addresses take no scalar registers through the step)
     const MonPtrs *mon;

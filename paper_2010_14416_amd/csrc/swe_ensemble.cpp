@@ -37,8 +37,6 @@ struct swe_ens {
     // concatenated inputs, uploaded at the first device use
     int64_t total_cells = 0, total_blocks = 0;
     std::vector<int32_t> blk_edge, be_a, be_b, blk_member, member_end;
-    std::vector<int32_t> blk_nbr;   // kNbrSlots per block
-    bool nbr_complete = true;
     std::vector<double> be_nx, be_ny, be_len, area, inr, z, man, h, hu, hv;
     std::vector<BcEntry> bc_slot;
     // device
@@ -55,8 +53,8 @@ struct swe_ens {
         Clock *clock;
         double *ledger;
         int32_t *quiet;
-        int32_t *blk_nbr;
         uint32_t *run;
+        unsigned long long *act;
         double *t_end;
     } d{};
     std::vector<double> t_end_host;   // as last uploaded
@@ -120,7 +118,7 @@ size_t ens_layout(swe_ens *e, char *base)
     e->d.clock = (Clock *)take(nm * sizeof(Clock));
     e->d.ledger = (double *)take(nb * 8);
     e->d.quiet = (int32_t *)take(nb * 4);
-    e->d.blk_nbr = (int32_t *)take(e->blk_nbr.size() * 4);
+    e->d.act = (unsigned long long *)take(nb * (e->block_cells / 64) * 8);
     e->d.run = (uint32_t *)take(2 * nb * 4);
     e->d.t_end = (double *)take(nm * 8);
     return off;
@@ -186,8 +184,6 @@ swe_status ens_prepare(swe_ens *e)
     if ((st = up(e, e->d.be_ny, e->be_ny.data(), nbe))) return st;
     if ((st = up(e, e->d.be_len, e->be_len.data(), nbe))) return st;
     if ((st = up(e, e->d.blk_member, e->blk_member.data(), nb))) return st;
-    if ((st = up(e, e->d.blk_nbr, e->blk_nbr.data(), e->blk_nbr.size())))
-        return st;
     if ((st = up(e, e->d.member_end, e->member_end.data(),
                  size_t(e->n_members))))
         return st;
@@ -202,6 +198,9 @@ swe_status ens_prepare(swe_ens *e)
     ENSCHK(e, swe::launch_fill_u32((unsigned *)e->d.quiet, 0u, int64_t(nb),
                                    e->stream));
     ENSCHK(e, swe::launch_fill_u32(e->d.run, 1u, 2 * int64_t(nb), e->stream));
+    ENSCHK(e, swe::launch_fill_u32((unsigned *)e->d.act, 0u,
+                                   int64_t(nb) * e->block_cells / 32,
+                                   e->stream));
     for (int32_t m = 0; m < e->n_members; ++m) {
         Clock *ck = e->d.clock + m;
         const int64_t c0 = e->cell_off[m];
@@ -306,10 +305,6 @@ swe_status swe_ens_create(swe_ens **out, swe_ctx *const *members,
     e->h.assign(nc, 0.0);
     e->hu.assign(nc, 0.0);
     e->hv.assign(nc, 0.0);
-    e->nbr_complete = true;
-    for (int32_t m = 0; m < n_members; ++m)
-        e->nbr_complete = e->nbr_complete && members[m]->mesh.nbr_complete;
-    e->blk_nbr.reserve(size_t(blocks) * swe::kNbrSlots);
     e->blk_edge.reserve(size_t(blocks) + 1);
     e->be_a.reserve(size_t(recs));
     e->be_b.reserve(size_t(recs));
@@ -355,8 +350,6 @@ swe_status swe_ens_create(swe_ens **out, swe_ctx *const *members,
         e->t_start.push_back(t);
         e->steps_start.push_back(steps);
         // blocks and records, with indices moved to the ensemble's ranges
-        for (const int32_t v : M.blk_nbr)
-            e->blk_nbr.push_back(v < 0 ? v : int32_t(v + e->blk_off[m]));
         for (int32_t b = 0; b < M.n_blocks; ++b) {
             e->blk_edge.push_back(int32_t(rec_off + M.blk_edge[b]));
             e->blk_member.push_back(int32_t(uint32_t(m) |
@@ -487,9 +480,8 @@ swe_status swe_ens_advance(swe_ens *e, int64_t steps, const double *t_end)
     a.clock = e->d.clock;
     a.ledger = e->d.ledger;
     a.quiet = e->d.quiet;
-    a.blk_nbr = e->d.blk_nbr;
     a.run = e->d.run;
-    a.skip_dormant = e->nbr_complete ? 1 : 0;
+    a.act = e->d.act;
     a.store_all = e->params.store_all;
     a.blk_member = e->d.blk_member;
     a.member_end = e->d.member_end;

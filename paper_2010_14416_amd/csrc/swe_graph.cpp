@@ -27,8 +27,8 @@ bool same_fixed_args(const StepArgs &x, const StepArgs &y)
     return SAME(blk_edge) && SAME(be_a) && SAME(be_b) && SAME(be_nx) &&
            SAME(be_ny) && SAME(be_len) && SAME(z) && SAME(gm2) &&
            SAME(area) && SAME(inradius) && SAME(bc) && SAME(clock) &&
-           SAME(ledger) && SAME(quiet) && SAME(blk_nbr) && SAME(run) &&
-           SAME(skip_dormant) && SAME(mon) && SAME(blk_member) &&
+           SAME(ledger) && SAME(quiet) && SAME(run) && SAME(act) &&
+           SAME(mon) && SAME(blk_member) &&
            SAME(member_end) && SAME(t_end_m) &&
            std::memcmp(&x.g, &y.g, sizeof x.g) == 0 &&
            std::memcmp(&x.cfl, &y.cfl, sizeof x.cfl) == 0 &&

@@ -74,9 +74,10 @@ __device__ __forceinline__ double wave_sum(double v)
 // End of a step for one block: wave-shuffle then LDS reductions of the
 // block's min R_i/s_i (one 64-bit atomic min into the next clock slot), of
 // the mass added by the positivity fix, and of the non-finite flag; block 0
-// advances the clock. Returns the block's new count of consecutive quiet
-// steps (capped at 2) to every thread.
-template <int NT>
+// advances the clock. Each wave of owned cells records which of them left
+// the quiet dry path (act_now and a.act). Returns the block's new count of
+// consecutive quiet steps (capped at 2) to every thread.
+template <int NC, int NT>
 __device__ __forceinline__ int block_finish(const StepArgs &a, int blk,
                                              Clock *clock, bool first,
                                              double rs, double clamp,
@@ -85,7 +86,8 @@ __device__ __forceinline__ int block_finish(const StepArgs &a, int blk,
                                              double dt, double tn,
                                              long long idx, int nxt,
                                              double *red_min, double *red_sum,
-                                             unsigned *red_bad)
+                                             unsigned *red_bad,
+                                             unsigned long long *act_now)
 {
     const int tid = threadIdx.x;
     rs = wave_min(rs);
@@ -97,6 +99,10 @@ __device__ __forceinline__ int block_finish(const StepArgs &a, int blk,
         red_min[wave] = rs;
         red_sum[wave] = clamp;
         red_bad[wave] = (ballot != 0ull ? 1u : 0u) | (busy != 0ull ? 2u : 0u);
+        if (wave < NC / 64) {
+            act_now[wave] = busy;
+            a.act[size_t(blk) * (NC / 64) + wave] = busy;
+        }
     }
     __syncthreads();
     unsigned busy_any = 0u;
@@ -202,6 +208,19 @@ __device__ __forceinline__ int xcd_block(int w, int n_blocks)
     return (j / kXcdChunk) * R + x * kXcdChunk + j % kXcdChunk;
 }
 
+// An edge record (va, vb) that joins a cell of this block to a cell x of
+// another: the first cell of x's block plus the local index of this
+// block's cell (below 2^30); else all ones.
+template <int NC>
+__device__ __forceinline__ uint32_t cross_mark(int32_t va, int32_t vb)
+{
+    const bool xa = uint32_t(va) < kSideBoundary;
+    const bool xb = uint32_t(vb) < kSideBoundary;
+    if (!xa && !xb) return 0xffffffffu;
+    return (uint32_t(xa ? va : vb) & ~uint32_t(NC - 1)) |
+           (uint32_t(xa ? vb : va) & uint32_t(NC - 1));
+}
+
 // One explicit step, one workgroup per block of NC consecutive cells and NT
 // threads (NC or 2 NC); threads below NC own a cell, all threads share the
 // block's edges (neighbour-block and boundary edges first, so that the
@@ -221,7 +240,7 @@ __device__ __forceinline__ int xcd_block(int w, int n_blocks)
 // the plain step keeps its registers.
 template <int NC, int NT, bool EAGER, bool MON, bool SLOT>
 __global__ __launch_bounds__(NT)
-__attribute__((amdgpu_waves_per_eu(SLOT ? 5 : 6)))
+__attribute__((amdgpu_waves_per_eu(6)))
 void swe_step_kernel(StepArgs a)
 {
     extern __shared__ double lds[];
@@ -229,7 +248,13 @@ void swe_step_kernel(StepArgs a)
     __shared__ double red_sum[NT / 64];
     __shared__ unsigned red_bad[NT / 64];
     __shared__ int4 s_bnd[1];
-    __shared__ int32_t s_nbr[kNbrSlots];
+    // per wave of owned cells: those not quiet in the block's last
+    // computed step, then those not quiet in this one
+    __shared__ unsigned long long s_act[2 * (NC / 64)];
+    // cross marks of the first edge records (records to other blocks come
+    // first; those past kMarks are read again at the end)
+    constexpr int kMarks = NT < 64 ? NT : 64;
+    __shared__ uint32_t s_mark[kMarks];
     double *s_h = lds;
     double *s_u = s_h + NC;
     double *s_v = s_u + NC;
@@ -251,12 +276,13 @@ void swe_step_kernel(StepArgs a)
         mem = code & 0x7fffffff;
         cell_end = a.member_end[mem];
     }
-    // dormant blocks: a block that, like each of its neighbour blocks, took
-    // the quiet dry path in the two previous steps has the inputs it had
-    // one step ago, so it would compute (and already holds) the same quiet
-    // results. No block of the previous step marked it to run: it returns
-    // before any other load (the clock's block always runs).
-    if (a.skip_dormant && !a.store_all && !first && run_me == 0u) {
+    // dormant blocks: a block whose cells took the quiet dry path in the two
+    // previous steps, as did every cell of another block that shares an
+    // edge with them, has the inputs it had one step ago, so it would
+    // compute (and already holds) the same quiet results. No block of the
+    // previous step marked it to run: it returns before any other load
+    // (the clock's block always runs).
+    if (!a.store_all && !first && run_me == 0u) {
         if (SLOT && a.run_log && tid == 0) a.run_log[blk] = 0;
         if (SLOT && tid < NC && blk * NC + tid < cell_end) {
             // a fresh output slot: carry the unchanged state over
@@ -311,8 +337,9 @@ void swe_step_kernel(StepArgs a)
         ea2 = a.be_a[e0 + tid + NT];
         eb2 = a.be_b[e0 + tid + NT];
     }
-    int32_t nbr = -1;   // neighbour blocks, to LDS with phase 1
-    if (tid < kNbrSlots) nbr = a.blk_nbr[blk * kNbrSlots + tid];
+    unsigned long long act_prev = 0ull;   // to s_act with phase 1
+    if (tid < NC && (tid & 63) == 0)
+        act_prev = a.act[size_t(blk) * (NC / 64) + (tid >> 6)];
     // the momentum of a dry cell is read in phase 3, and only if needed
     if (owner && h > h_dry) {
         hu = a.hu0[i];
@@ -343,7 +370,9 @@ void swe_step_kernel(StepArgs a)
     }
     const StepTime st = step_time(a, cw, t_end);
     if (MON && tid == NC / 64) s_bnd[0] = bnd;
-    if (tid < kNbrSlots) s_nbr[tid] = nbr;
+    if (tid < kMarks)
+        s_mark[tid] = tid < ne ? cross_mark<NC>(ea, eb) : 0xffffffffu;
+    if (tid < NC && (tid & 63) == 0) s_act[tid >> 6] = act_prev;
     if (owner) {
         s_h[tid] = h;
         s_z[tid] = zc;
@@ -495,21 +524,39 @@ void swe_step_kernel(StepArgs a)
             rs = inr / (sqrt(g * hn) + sqrt(u * u + v * v));
         }
     }
-    const int q = block_finish<NT>(a, blk, clock, first, rs, clamp, bad,
+    const int q = block_finish<NC, NT>(a, blk, clock, first, rs, clamp, bad,
                                    active, quiet_steps, st.unbounded, st.dt,
                                    st.tn, st.idx, a.cur == 2 ? 0 : a.cur + 1,
                                    red_min,
-                                   red_sum, red_bad);
+                                   red_sum, red_bad, s_act + NC / 64);
     {
         // this step's mark is used up; a block not quiet for two steps
-        // marks itself and its neighbour blocks to run at the next step
+        // marks itself to run at the next step, and each edge from a cell
+        // that may have changed marks the other block it reaches
         const size_t next = size_t(a.n_blocks) - run_at;
         if (tid == 0 && run_me) a.run[run_at + blk] = 0u;
         if (SLOT && tid == 0 && a.run_log) a.run_log[blk] = 1;
         if (q < 2) {
             if (tid == 0) a.run[next + blk] = 1u;
-            if (tid < kNbrSlots && s_nbr[tid] >= 0)
-                a.run[next + s_nbr[tid]] = 1u;
+            // a cell may have changed in this step if it was not quiet in
+            // it or in the block's last computed step (a cell quiet in both
+            // holds (h, 0, 0) before and after)
+            auto mark = [&](uint32_t m) {
+                const uint32_t l = m & uint32_t(NC - 1);
+                const unsigned long long w =
+                    s_act[l >> 6] | s_act[NC / 64 + (l >> 6)];
+                if (m != 0xffffffffu && (w >> (l & 63)) & 1ull)
+                    a.run[next + m / NC] = 1u;
+            };
+            if (tid < kMarks) mark(s_mark[tid]);
+            // more records to other blocks past the first kMarks only if
+            // record kMarks - 1 is one
+            const bool more = s_mark[kMarks - 1] != 0xffffffffu;
+            for (int k = kMarks + tid; more && k < ne; k += NT) {
+                const uint32_t m = cross_mark<NC>(a.be_a[e0 + k], a.be_b[e0 + k]);
+                if (m == 0xffffffffu) break;
+                mark(m);
+            }
         }
     }
     // the stores come last: no instruction after them waits for a load, so

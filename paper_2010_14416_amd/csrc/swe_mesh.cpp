@@ -731,28 +731,6 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
         }
     }
 
-    // ---- neighbour blocks: those holding the other cell of a cross edge
-    M.blk_nbr.assign(size_t(nblk) * kNbrSlots, -1);
-    bool fits = true;
-#pragma omp parallel for schedule(static) reduction(&& : fits)
-    for (int64_t b = 0; b < nblk; ++b) {
-        int32_t *slot = M.blk_nbr.data() + size_t(b) * kNbrSlots;
-        int n = 0;
-        for (int32_t r = M.blk_edge[b]; r < M.blk_edge[b + 1]; ++r)
-            for (const int32_t v : {M.be_a[r], M.be_b[r]}) {
-                if (uint32_t(v) >= kSideBoundary) continue;   // own or slot
-                const int32_t nb_blk = int32_t(v / B);
-                bool seen = false;
-                for (int k = 0; k < n; ++k) seen = seen || slot[k] == nb_blk;
-                if (seen) continue;
-                if (n == kNbrSlots) {
-                    fits = false;
-                    continue;
-                }
-                slot[n++] = nb_blk;
-            }
-    }
-    M.nbr_complete = fits;
     return true;
 }
 

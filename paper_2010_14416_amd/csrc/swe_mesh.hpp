@@ -48,18 +48,9 @@ struct BlockMesh {
     std::vector<int32_t> bnd_tag;
     std::vector<int32_t> blk_bnd;
 
-    // per block kNbrSlots entries: the other blocks it shares an edge with,
-    // then -1; nbr_complete is false if some block has more (dormant blocks
-    // are then never skipped)
-    std::vector<int32_t> blk_nbr;
-    bool nbr_complete = true;
-
     // total boundary length per tag (inflow discharge per unit length)
     std::vector<double> tag_length;
 };
-
-// Neighbour blocks kept per block for skipping dormant blocks.
-constexpr int kNbrSlots = 64;
 
 // Edges given by the caller instead of discovered from the triangles:
 // n edges, nodes[2e], nodes[2e+1] (either order), cells[2e], cells[2e+1]
