@@ -39,7 +39,8 @@ PEAK_HBM_GBS = 8000.0           # MI355X HBM3E, published
 ALG_BYTES_PER_CELL = 140
 KERNEL_SRC = [os.path.join(ROOT, "paper_2010_14416_amd", "csrc", f)
               for f in ("swe_kernels.hip", "swe_scheme.hpp", "swe_device.hpp",
-                        "swe_mesh.hpp")]
+                        "swe_mesh.hpp")] + [
+    os.path.join(ROOT, "paper_2010_14416_amd", "build.py")]   # its flags
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 
 

@@ -212,14 +212,14 @@ swe_status swe_set_wet_cells(swe_ctx *ctx, int64_t n_cells,
 swe_status swe_mesh_info(const swe_ctx *ctx, swe_mesh_stats *out);
 
 /* Blocks the next step will compute, and the cells they hold (the others
- * are dormant: dry, quiet for two steps with quiet neighbour blocks, and
- * skipped). A measurement aid: the work a step does depends on the state.
+ * are dormant: dry and quiet for two steps, as are the cells of other
+ * blocks they share an edge with, and skipped). A measurement aid: the work a step does depends on the state.
  * Synchronises the stream. */
 swe_status swe_get_activity(swe_ctx *ctx, int64_t *blocks, int64_t *cells);
 
 /* 64-bit digest (FNV-1a) of the internal mesh the step reads: cell order,
  * areas, inscribed radii, block edge records, normals, lengths, boundary
- * slots and tags, neighbour blocks. Two ways of giving the same mesh (edges
+ * slots and tags. Two ways of giving the same mesh (edges
  * discovered or listed) yield the same digest. Host only. */
 swe_status swe_mesh_digest(const swe_ctx *ctx, uint64_t *digest);
 

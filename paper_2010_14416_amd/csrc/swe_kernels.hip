@@ -16,7 +16,11 @@
 //   5. the block's minimum of R_i / s_i (wave shuffles, then LDS) goes to the
 //      clock with one 64-bit atomic min on the bit pattern (positive doubles
 //      order as unsigned integers), so the next step finds its time step on
-//      the device without a host round trip.
+//      the device without a host round trip;
+//   6. it marks the blocks that must run in the next step: itself unless
+//      quiet for two steps, and, across each edge to another block, that
+//      block if the cell on this side left the quiet dry path in this step
+//      or the block's previous computed one. Unmarked blocks are dormant.
 // State and geometry are FP64 structure-of-arrays, read once per step with
 // coalesced loads; edges on a block border are evaluated by both blocks.
 //
