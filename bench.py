@@ -65,6 +65,9 @@ def make_case(args):
             "jittered-point Delaunay mesh, thalweg + Perlin bed, Manning "
             "U[0.02,0.05], inflow 500 m^3/s, fixed outlet stage, partly dry "
             "floodplain")
+    if args.workload == "wetcanal":
+        return W.wet_canal(), ("wet-canal-13M: 3600x1806 squares, every cell "
+                               "wet and flowing, flat bed, Manning 0.03")
     if args.workload == "bumps":
         return W.bumps_canal(), ("bumps-canal-1M: 1000x500 squares, dam break "
                                  "onto a dry bed over 20 Gaussian bumps, "
@@ -221,6 +224,39 @@ def _read_counter_csv(path, counter):
     return out
 
 
+def _step_values(d, select=""):
+    """Values of the plain step kernel (not the adjoint's fresh-slot
+    instantiation) from _read_counter_csv, dispatches lo:hi if `select`."""
+    ks = [k for k in d if "swe_step_kernel" in k and not re.search(
+        r"swe_step_kernel<\d+, \d+, \w+, \w+, true>", k)]
+    if not ks:
+        raise SystemExit("no dispatch of the step kernel")
+    vals = [v for k in ks for v in d[k]]
+    if select:
+        lo, hi = (int(x) if x else None for x in select.split(":"))
+        vals = vals[lo:hi]
+    return vals
+
+
+def pmc_table(path, select, cells):
+    """Every counter of one rocprofv3 --pmc run, averaged over the step
+    kernel's dispatches `select` ("lo:hi"), per launch and per computed
+    cell-lane (x 64 for the SQ_INSTS_* wave counts)."""
+    import csv
+    with open(path, newline="") as f:
+        names = sorted({r["Counter_Name"] for r in csv.DictReader(f)})
+    out = {}
+    for c in names:
+        vals = _step_values(_read_counter_csv(path, c), select)
+        per = sum(vals) / len(vals)
+        out[c] = dict(per_launch=per, dispatches=len(vals))
+        if cells:
+            out[c]["per_cell"] = per * (64 if c.startswith("SQ_INSTS") else
+                                        1) / cells
+    print(json.dumps(out, indent=1))
+    return out
+
+
 def pmc_summary(fetch_csv, write_csv, copy_mb, n_cells, out_path,
                 valu_csv=None, steps="", select=""):
     """Per-launch HBM traffic of the step kernel from two rocprofv3 --pmc
@@ -237,15 +273,12 @@ def pmc_summary(fetch_csv, write_csv, copy_mb, n_cells, out_path,
     write = _read_counter_csv(write_csv, "WRITE_SIZE")
 
     def pick(d, key):
-        # the plain step, not its fresh-slot instantiation (the adjoint's)
-        ks = [k for k in d if key in k and not re.search(
-            r"swe_step_kernel<\d+, \d+, \w+, \w+, true>", k)]
-        if not ks:
+        if key == "swe_step_kernel":
+            vals = _step_values(d, select)
+        else:
+            vals = [v for k in d if key in k for v in d[k]]
+        if not vals:
             raise SystemExit(f"no dispatch of a kernel matching {key!r}")
-        vals = [v for k in ks for v in d[k]]
-        if select and key == "swe_step_kernel":
-            lo, hi = (int(x) for x in select.split(":"))
-            vals = vals[lo:hi]
         return sum(vals) / len(vals), len(vals)
 
     known = copy_mb * (1 << 20)
@@ -289,8 +322,8 @@ def main():
                     help="timed steps (1000; 500 for the ensemble)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="river",
-                    choices=["river", "bumps", "canal", "ensemble",
-                             "adjoint"])
+                    choices=["river", "bumps", "canal", "wetcanal",
+                             "ensemble", "adjoint"])
     ap.add_argument("--cells", type=int, default=13_000_000)
     ap.add_argument("--run-steps", type=int, default=1000,
                     help="step count of the workload's run: the steps after "
@@ -332,12 +365,21 @@ def main():
                     help="with --pmc-summary: lo:hi, the step-kernel "
                          "dispatches (in order) to average")
     ap.add_argument("--pmc-out", default=TRAFFIC_FILE)
+    ap.add_argument("--pmc-table", default=None, metavar="CSV",
+                    help="print every counter of one --pmc run for the step "
+                         "kernel's dispatches --pmc-dispatches, per launch "
+                         "and per cell of --pmc-table-cells")
+    ap.add_argument("--pmc-table-cells", type=float, default=None)
     ap.add_argument("--pmc-cells", type=int, default=13_004_176,
                     help="cell count of the profiled workload")
     ap.add_argument("--members", type=int, default=256,
                     help="ensemble members (--workload ensemble)")
     ap.add_argument("--solo-sample", type=int, default=16,
                     help="ensemble members also timed one at a time")
+    ap.add_argument("--ens-shape", default=None, metavar="NC,BAND,THREADS",
+                    help="ensemble launch shape (block cells, wet band, "
+                         "threads per block, 0 = automatic) instead of the "
+                         "autotuner's choice")
     ap.add_argument("--no-autotune", action="store_true",
                     help="ensemble: 64-cell blocks, band 2, no tuning")
     ap.add_argument("--no-every-block", action="store_true",
@@ -362,6 +404,9 @@ def main():
         args.steps = {"ensemble": 500, "adjoint": 2000}.get(args.workload,
                                                             1000)
 
+    if args.pmc_table:
+        pmc_table(args.pmc_table, args.pmc_dispatches, args.pmc_table_cells)
+        return
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_mb,
                     args.pmc_cells, args.pmc_out, args.pmc_valu,
@@ -642,6 +687,9 @@ def leg_ensemble(args, steps, warmup, solo, tune, tune_sample=32,
     log(f"ensemble: {len(cases)} members, {n} cells "
         f"({time.perf_counter() - t0:.1f} s to generate)")
     best, table = (64, 2, 0), {}
+    if args.ens_shape:
+        best = tuple(int(x) for x in args.ens_shape.split(","))
+        tune = False
     if tune:
         t0 = time.perf_counter()
         best, table = S.autotune_ensemble(cases, sample=tune_sample,
@@ -671,6 +719,15 @@ def leg_ensemble(args, steps, warmup, solo, tune, tune_sample=32,
         ens.time(k)                       # raises on a numeric fault
     log(f"ensemble: {steps} steps in {ens_ms:.2f} ms ({info['n_blocks']} "
         "blocks)")
+    # cells the next 10 steps compute (the rest dormant), one step at a time
+    act = []
+    for _ in range(10):
+        act.append(ens.activity()[1])
+        ens.advance(1)
+    ens.time(0)
+    computed = float(np.mean(act))
+    log(f"ensemble: cells computed per step {computed:.0f} of {n} "
+        f"({computed / n:.3f})")
     k_sample = max(1, min(solo, len(cases)))
     pick = np.linspace(0, len(cases) - 1, k_sample).round().astype(int)
     solo_ms = {0: [], 96: []}
@@ -693,10 +750,12 @@ def leg_ensemble(args, steps, warmup, solo, tune, tune_sample=32,
     value = n * steps / (ens_ms * 1e-3)
     ms_per_step = ens_ms / steps
     eff = ALG_BYTES_PER_CELL * n / (ms_per_step * 1e-3) / 1e9
+    ach = ALG_BYTES_PER_CELL * computed / (ms_per_step * 1e-3) / 1e9
     return dict(
         value=value, members=len(cases), n_cells=n, steps=steps,
         timed_steps=f"{pre + 1}..{pre + steps}",
         ensemble_ms=ens_ms, ms_per_step=ms_per_step,
+        cells_computed_frac=computed / n,
         block_cells=best[0], wet_band=best[1], block_threads=best[2],
         autotune={f"cells {bc} band {b} threads {t or bc}": ms
                   for (bc, b, t), ms in table.items()},
@@ -712,9 +771,12 @@ def leg_ensemble(args, steps, warmup, solo, tune, tune_sample=32,
                     n_cells=n, members=len(cases),
                     n_blocks=info["n_blocks"], setup_s=round(setup_s, 2),
                     effective_gbs=eff),
-        roofline=dict(bound="hbm", achieved=eff, peak=PEAK_HBM_GBS,
-                      unit="GB/s", frac=eff / PEAK_HBM_GBS, traffic=None,
-                      note="140 B x every cell of every member per step"))
+        roofline=dict(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS,
+                      unit="GB/s", frac=ach / PEAK_HBM_GBS, traffic=None,
+                      cells_computed_per_launch=computed,
+                      effective_gbs_all_cells=eff,
+                      note="140 B x the cells of the blocks computed per "
+                           "step (the 10 steps after the timed ones)"))
 
 
 def smooth_direction(case, rng):

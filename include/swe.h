@@ -405,7 +405,10 @@ swe_status swe_get_envelope(swe_ctx *ctx, double *h_max, double *t_wet,
  * non-finite state or an unbounded time step.
  * swe_ens_workspace_bytes / swe_ens_bind_workspace: as for a context,
  * before the first advance.
- * swe_ens_info: cells of all members and mesh blocks. */
+ * swe_ens_info: cells of all members and mesh blocks.
+ * swe_ens_get_activity: as swe_get_activity, over all members: blocks the
+ * next step computes and the member cells they hold. Synchronises the
+ * stream. */
 typedef struct swe_ens swe_ens;
 
 swe_status swe_ens_create(swe_ens **out, swe_ctx *const *members,
@@ -422,6 +425,8 @@ swe_status swe_ens_get_time(swe_ens *ens, int32_t member, double *t,
                             double *last_dt, int64_t *steps);
 swe_status swe_ens_info(const swe_ens *ens, int64_t *n_cells,
                         int64_t *n_blocks);
+swe_status swe_ens_get_activity(swe_ens *ens, int64_t *blocks,
+                                int64_t *cells);
 
 /* Device memory: by default the library allocates it on first use. A
  * caller that owns device memory (e.g. a torch uint8 tensor) can instead

@@ -573,6 +573,36 @@ swe_status swe_ens_get_state(swe_ens *e, int32_t member, double *h,
     return SWE_OK;
 }
 
+swe_status swe_ens_get_activity(swe_ens *e, int64_t *blocks, int64_t *cells)
+{
+    if (!e) return SWE_EINVAL;
+    swe_status st = ens_prepare(e);
+    if (st) return st;
+    const int64_t nb = e->total_blocks, B = e->block_cells;
+    // the kernel's test: store_all off, the mark of this step's parity
+    // clear, and not a member's first block (it advances the clock)
+    std::vector<uint32_t> mark(size_t(nb), 1u);
+    if (!e->params.store_all) {
+        ENSCHK(e, hipMemcpyAsync(mark.data(),
+                                 e->d.run + size_t(e->step_index & 1) * nb,
+                                 size_t(nb) * 4, hipMemcpyDeviceToHost,
+                                 e->stream));
+        ENSCHK(e, hipStreamSynchronize(e->stream));
+    }
+    int64_t b = 0, n = 0;
+    for (int64_t k = 0; k < nb; ++k) {
+        const int32_t code = e->blk_member[size_t(k)];
+        if (!mark[size_t(k)] && code >= 0) continue;
+        const int32_t m = code & 0x7fffffff;
+        ++b;
+        n += std::max<int64_t>(0, std::min<int64_t>(B, e->member_end[m] -
+                                                           k * B));
+    }
+    if (blocks) *blocks = b;
+    if (cells) *cells = n;
+    return SWE_OK;
+}
+
 swe_status swe_ens_info(const swe_ens *e, int64_t *n_cells, int64_t *n_blocks)
 {
     if (!e) return SWE_EINVAL;

@@ -181,6 +181,8 @@ def load():
     L.swe_ens_get_time.argtypes = [_p, C.c_int32, _pd, _pd, _pi64]
     L.swe_ens_info.restype = st
     L.swe_ens_info.argtypes = [_p, _pi64, _pi64]
+    L.swe_ens_get_activity.restype = st
+    L.swe_ens_get_activity.argtypes = [_p, _pi64, _pi64]
     L.swe_workspace_bytes.restype = st
     L.swe_workspace_bytes.argtypes = [_p, C.POINTER(C.c_size_t)]
     L.swe_bind_workspace.restype = st
@@ -613,6 +615,13 @@ def swe_ens_info(ens):
     return dict(n_cells=n.value, n_blocks=b.value)
 
 
+def swe_ens_get_activity(ens):
+    """(blocks, cells) the ensemble's next step computes."""
+    b, c = C.c_int64(), C.c_int64()
+    _echeck(ens, load().swe_ens_get_activity(ens, C.byref(b), C.byref(c)))
+    return b.value, c.value
+
+
 # ------------------------------------------------------------ convenience
 
 class Solver:
@@ -768,6 +777,9 @@ class Ensemble:
 
     def info(self):
         return swe_ens_info(self.ens)
+
+    def activity(self):
+        return swe_ens_get_activity(self.ens)
 
 
     def close(self):

@@ -97,6 +97,33 @@ def test_dormant_blocks_change_no_member_bit():
         assert a.time(k) == b.time(k)
 
 
+def test_activity_is_the_sum_of_the_members_activities():
+    """The blocks an ensemble step computes are those its members compute
+    alone with the same block size and band: swe_ens_get_activity equals
+    the sum of the members' swe_get_activity, as the run goes from every
+    block computed to mostly dormant."""
+    from paper_2010_14416_amd import Ensemble, Solver, swe as S
+    cases = members()
+    ens = Ensemble(cases)
+    alone = [Solver(c, device=0, block_cells=64, wet_band=2) for c in cases]
+    done = 0
+    for at in (0, 1, 3, 40, 150):
+        if at > done:
+            ens.advance(at - done)
+            for s in alone:
+                s.advance(at - done)
+        done = at
+        b, c = ens.activity()
+        parts = [S.swe_get_activity(s.ctx) for s in alone]
+        say(f"  step {at}: ensemble {b} blocks {c} cells; members "
+            f"{sum(p[0] for p in parts)} / {sum(p[1] for p in parts)}")
+        assert (b, c) == (sum(p[0] for p in parts), sum(p[1] for p in parts))
+    assert c < sum(x.n_cells for x in cases)   # some blocks fell dormant
+    for s in alone:
+        s.close()
+    ens.close()
+
+
 def test_full_size_ensemble_sampled_members_match_their_own_runs():
     """The benchmarked configuration (256 members, 27.7 M cells, the
     Ensemble's defaults): sampled members after 100 steps equal, bit for

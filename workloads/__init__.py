@@ -234,6 +234,24 @@ def bumps_canal(nx: int = 1000, ny: int = 500, lx: float = 100.0,
                 meta=dict(seed=seed, lx=lx, ly=ly))
 
 
+def wet_canal(nx: int = 3600, ny: int = 1806, manning: float = 0.03,
+              h_left: float = 2.0, h_right: float = 1.0,
+              u0: float = 0.5) -> Case:
+    """Every cell wet and moving: squares of 1 m, flat bed, Manning n
+    uniform, depth h_left upstream of the middle and h_right downstream, all
+    with velocity u0 along the canal, walls all round. The step's uniform
+    case: every edge a wet-wet flux, every cell a Manning update (13 M cells
+    by default)."""
+    xy, tri, bnd, tag = canal_mesh(nx, ny, float(nx), float(ny))
+    n = tri.shape[0]
+    cx = xy[tri].mean(axis=1)[:, 0]
+    h = np.where(cx < nx / 2.0, h_left, h_right).astype(np.float64)
+    return Case(name=f"wet-canal-{nx}x{ny}", xy=xy, tri=tri, bnd=bnd,
+                bnd_tag=tag, bc={}, z=_zeros(n), manning=np.full(n, manning),
+                h=h, hu=u0 * h, hv=_zeros(n), steps=1000,
+                meta=dict(lx=float(nx), ly=float(ny)))
+
+
 def lake_at_rest(nx: int = 100, ny: int = 40, lx: float = 100.0,
                  ly: float = 20.0, seed: int = 2, eta: float = 0.12,
                  manning: float = 0.03, steps: int = 2000) -> Case:
