@@ -231,8 +231,9 @@ __device__ __forceinline__ uint32_t cross_mark(int32_t va, int32_t vb)
 // first NT of them hold every edge that needs a neighbour's state).
 //
 // Before the first barrier each thread requests its owned cell and its
-// edge records, then the neighbour-block state of its first edge; the cell
-// geometry of wet cells is requested before the second barrier.
+// edge records, then, in one second round trip, the state of its first
+// edge's neighbour in another block and its cell's momentum if wet; the
+// cell geometry of wet cells is requested before the second barrier.
 // EAGER: the geometry of every edge and cell is requested with them.
 // Otherwise inputs that cannot change the result are skipped: the geometry
 // of an edge between two cells holding no water is never read, and a dry
@@ -255,10 +256,6 @@ void swe_step_kernel(StepArgs a)
     // per wave of owned cells: those not quiet in the block's last
     // computed step, then those not quiet in this one
     __shared__ unsigned long long s_act[2 * (NC / 64)];
-    // cross marks of the first edge records (records to other blocks come
-    // first; those past kMarks are read again at the end)
-    constexpr int kMarks = NT < 64 ? NT : 64;
-    __shared__ uint32_t s_mark[kMarks];
     double *s_h = lds;
     double *s_u = s_h + NC;
     double *s_v = s_u + NC;
@@ -344,24 +341,29 @@ void swe_step_kernel(StepArgs a)
     unsigned long long act_prev = 0ull;   // to s_act with phase 1
     if (tid < NC && (tid & 63) == 0)
         act_prev = a.act[size_t(blk) * (NC / 64) + (tid >> 6)];
-    // the momentum of a dry cell is read in phase 3, and only if needed
-    if (owner && h > h_dry) {
-        hu = a.hu0[i];
-        hv = a.hv0[i];
-    }
     // a side coded as a plain internal index (below kSideBoundary) is a
     // cell of another block
     CellState X;
+    // the thread's first and second edge records, if they join a cell of
+    // this block to one of another (cross_mark), for the run marks
+    uint32_t xmark = 0xffffffffu, xmark2 = 0xffffffffu;
     {
         double xh = 0.0, xhu = 0.0, xhv = 0.0, xz = 0.0;
         const bool xa = uint32_t(ea) < kSideBoundary;
         const bool xb = uint32_t(eb) < kSideBoundary;
         if (tid < ne && (xa || xb)) {
             const int x = xa ? ea : eb;
+            xmark = cross_mark<NC>(ea, eb);
             xh = a.h0[x];
             xhu = a.hu0[x];
             xhv = a.hv0[x];
             xz = a.z[x];
+        }
+        // the momentum of a dry cell is read in phase 3, and only if needed
+        // (requested after the neighbour state, whose address arrived first)
+        if (owner && h > h_dry) {
+            hu = a.hu0[i];
+            hv = a.hv0[i];
         }
         X.h = xh;
         X.z = xz;
@@ -374,8 +376,6 @@ void swe_step_kernel(StepArgs a)
     }
     const StepTime st = step_time(a, cw, t_end);
     if (MON && tid == NC / 64) s_bnd[0] = bnd;
-    if (tid < kMarks)
-        s_mark[tid] = tid < ne ? cross_mark<NC>(ea, eb) : 0xffffffffu;
     if (tid < NC && (tid & 63) == 0) s_act[tid >> 6] = act_prev;
     if (owner) {
         s_h[tid] = h;
@@ -453,6 +453,8 @@ void swe_step_kernel(StepArgs a)
         if (k != tid + NT) {
             va = a.be_a[e0 + k];
             vb = a.be_b[e0 + k];
+        } else {
+            xmark2 = cross_mark<NC>(va, vb);
         }
         double enx = 0.0, eny = 0.0, elen = 0.0;
         if (EAGER) {
@@ -552,11 +554,12 @@ void swe_step_kernel(StepArgs a)
                 if (m != 0xffffffffu && (w >> (l & 63)) & 1ull)
                     a.run[next + m / NC] = 1u;
             };
-            if (tid < kMarks) mark(s_mark[tid]);
-            // more records to other blocks past the first kMarks only if
-            // record kMarks - 1 is one
-            const bool more = s_mark[kMarks - 1] != 0xffffffffu;
-            for (int k = kMarks + tid; more && k < ne; k += NT) {
+            mark(xmark);
+            mark(xmark2);
+            // records to other blocks come first: past the thread's second
+            // record only if that one reaches another block
+            for (int k = tid + 2 * NT; xmark2 != 0xffffffffu && k < ne;
+                 k += NT) {
                 const uint32_t m = cross_mark<NC>(a.be_a[e0 + k], a.be_b[e0 + k]);
                 if (m == 0xffffffffu) break;
                 mark(m);
