@@ -12,9 +12,9 @@
  * Every function names the passage of the paper it follows. Where the paper
  * is silent, ambiguous or garbled, the comment says "reading:" and states the
  * interpretation taken. Pins of each function are in tests/test_oracle_*.py;
- * the wall boundary under impinging flow and the fixed-depth / fixed-stage
- * boundaries have no closed form and are parity-unpinned beyond their
- * consistency cases.
+ * the wall under impinging flow and the fixed-depth / fixed-stage ghosts,
+ * which have no closed form, are pinned by balance laws and by equivalent
+ * interior edges.
  *
  * Structure of one step, in the paper's order:
  *   1. time step from the current state (eq. 15, per-cell form of sec. 5.3.2)

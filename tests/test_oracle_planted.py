@@ -61,6 +61,17 @@ PLANTED = {
                         "        break;\n    }",
                         "        G[1] = 0.5 * g * g * hi * hi;\n"
                         "        G[2] = 0.0;\n        break;\n    }"),
+    # reflective wall: HLLC against the mirror state instead of the
+    # hydrostatic pressure alone (reading R11)
+    "wall_mirror_riemann": ("        G[0] = 0.0;\n        G[1] = 0.5 * g * hi * hi;\n"
+                            "        G[2] = 0.0;\n        break;\n    }",
+                            "        ora_hllc(g, h_dry, hi, un, ut, hi, -un, ut, G);\n"
+                            "        break;\n    }"),
+    # wall passing the momentum carried into it as well
+    "wall_convective": ("        G[1] = 0.5 * g * hi * hi;\n        G[2] = 0.0;\n"
+                        "        break;\n    }",
+                        "        G[1] = 0.5 * g * hi * hi + hi * un * un;\n"
+                        "        G[2] = 0.0;\n        break;\n    }"),
     # inflow entering with the outward sign
     "inflow_sign": ("G[0] = -q;", "G[0] = q;"),
     # diameter-free inscribed radius slip, A / perimeter

@@ -306,3 +306,64 @@ def test_mesh_errors(kind):
         tag = np.array([5000], np.int32)
     with pytest.raises(O.OracleError):
         O.Oracle(make(xy, tri, bnd, tag))
+
+
+# ------------------------------------------------------- wall momentum balance
+
+def test_wall_momentum_balance_under_impinging_flow():
+    """Reading R11 (sec. 3.1): a wall edge passes only the hydrostatic
+    pressure of its cell, g h^2 / 2 along the outward normal, whatever the
+    velocity into the wall. On a flat, frictionless, closed basin the
+    interior fluxes cancel in pairs and the bed adds nothing, so over one
+    step the total momentum changes by exactly -dt * sum over wall edges of
+    L (g/2) h_cell^2 n. The flow here runs obliquely into every wall; a
+    mirror-state Riemann wall, a velocity-dependent wall flux or a wrong
+    pressure factor breaks the balance at order one."""
+    case = W.dam_break_canal(nx=60, ny=20, lx=60.0, ly=20.0)
+    xy, tri = case.xy, case.tri.astype(np.int64)
+    cen = xy[tri].mean(axis=1)
+    n = tri.shape[0]
+    case.h = 1.0 + 0.2 * np.sin(0.21 * cen[:, 0]) * np.cos(0.37 * cen[:, 1])
+    case.hu = case.h * (0.8 + 0.3 * np.cos(0.17 * cen[:, 1]))
+    case.hv = case.h * (-0.6 + 0.2 * np.sin(0.11 * cen[:, 0]))
+    case.manning = np.zeros(n)
+    case.z = np.zeros(n)
+    o = O.Oracle(case)
+    h0, hu0, hv0 = o.state()
+    dt = 0.01
+    o.run_dt(np.array([dt]))
+    h1, hu1, hv1 = o.state()
+    # areas (shoelace) and the wall edges with their cell, length and
+    # outward normal, from the mesh alone
+    a, b, c = xy[tri[:, 0]], xy[tri[:, 1]], xy[tri[:, 2]]
+    area = 0.5 * np.abs((b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) -
+                        (c[:, 0] - a[:, 0]) * (b[:, 1] - a[:, 1]))
+    owner = {}
+    for t in range(n):
+        for k in range(3):
+            p, q = int(tri[t, k]), int(tri[t, (k + 1) % 3])
+            owner.setdefault((min(p, q), max(p, q)), []).append(t)
+    fx = fy = 0.0
+    walls = 0
+    for (p, q), cells in owner.items():
+        if len(cells) != 1:
+            continue
+        t = cells[0]
+        d = xy[q] - xy[p]
+        L = math.hypot(d[0], d[1])
+        nrm = np.array([d[1], -d[0]]) / L
+        if np.dot(nrm, xy[p] - cen[t]) < 0.0:       # point away from the cell
+            nrm = -nrm
+        pres = L * 0.5 * G * h0[t] ** 2
+        fx += pres * nrm[0]
+        fy += pres * nrm[1]
+        walls += 1
+    assert walls == 2 * (60 + 20)
+    # the flow impinges on the walls: momentum normal to them is not small
+    assert np.max(np.abs(hu0)) > 0.5 and np.max(np.abs(hv0)) > 0.3
+    dmx = math.fsum(area * (hu1 - hu0))
+    dmy = math.fsum(area * (hv1 - hv0))
+    assert abs(dmx - (-dt * fx)) <= 1e-11 * abs(dt * fx)
+    assert abs(dmy - (-dt * fy)) <= 1e-11 * max(abs(dt * fy), 1e-3)
+    # mass is untouched by the walls
+    assert abs(math.fsum(area * (h1 - h0))) <= 1e-12 * math.fsum(area * h0)
