@@ -634,6 +634,12 @@ def sweep_one(args, case, shape):
                 params={"block_threads": bt, "load_schedule": sched,
                         "monitors": mon, "store_all": sall})
     sw.advance(args.warmup + 1, want_time=True)
+    # 0.2 s of untimed steps of another context first, as for the main
+    # timing (a GPU fresh from host work runs this step slower at first)
+    warm = warmer(case, block_cells=bc, group_wet=not args.no_group_wet,
+                  wet_band=args.wet_band, params={"block_threads": bt})
+    warm()
+    warm.close()
     ms = ev_time(sw.stream, lambda: sw.advance(args.steps)) / args.steps
     sw.time()
     log(f"sweep {bc}x{bt} schedule {sched} monitors {mon} store_all "
