@@ -77,8 +77,9 @@ def hllc(g, h_dry, hL, uL, vL, hR, uR, vR):
     FR0, FR1, FR2 = hR * uR, hR * uR * uR + 0.5 * g * hR * hR, hR * uR * vR
     star = any_wet & (SL < 0.0) & (SR > 0.0)
     D = _w(star, SR - SL, one)
-    S0 = (SR * FL0 - SL * FR0 + SR * SL * (hR - hL)) / D
-    S1 = (SR * FL1 - SL * FR1 + SR * SL * (hR * uR - hL * uL)) / D
+    rD = 1.0 / D          # one reciprocal, as in the C oracle
+    S0 = (SR * FL0 - SL * FR0 + SR * SL * (hR - hL)) * rD
+    S1 = (SR * FL1 - SL * FR1 + SR * SL * (hR * uR - hL * uL)) * rD
     S2 = S0 * _w(Ss >= 0.0, vL, vR)
     left = SL >= 0.0
     G0 = _w(left, FL0, _w(SR <= 0.0, FR0, S0))
@@ -129,7 +130,8 @@ class TorchScheme:
     def _velocity(self, h, hu, hv):
         wet = h > self.h_dry
         hs = _w(wet, h, torch.ones_like(h))
-        return _w(wet, hu / hs, 0 * hu), _w(wet, hv / hs, 0 * hv)
+        r = 1.0 / hs
+        return _w(wet, hu * r, 0 * hu), _w(wet, hv * r, 0 * hv)
 
     def step(self, h, hu, hv, z, m, dt):
         g, h_dry = self.g, self.h_dry
@@ -199,7 +201,8 @@ class TorchScheme:
                 acc = acc + _w(self.c_right[:, s], cr[k][e], cl[k][e])
             R.append(acc)
         A = self.area
-        bh, bx, by = R[0] / A, R[1] / A, R[2] / A
+        rA = 1.0 / A
+        bh, bx, by = R[0] * rA, R[1] * rA, R[2] * rA
         dh = dt * bh
         with torch.no_grad():
             qn_raw = torch.sqrt(hu * hu + hv * hv)
@@ -209,19 +212,21 @@ class TorchScheme:
         qn = torch.sqrt(_w(fric, hu * hu + hv * hv, one))
         c = g * m * m / (hf * hf * torch.pow(hf, 1.0 / 3.0))
         sfx, sfy = -c * qn * hu, -c * qn * hv
-        jhx = (7.0 / 3.0) * c * qn * hu / hf
-        jhy = (7.0 / 3.0) * c * qn * hv / hf
-        jxx = -c * (qn + hu * hu / qn)
-        jxy = -c * hu * hv / qn
-        jyy = -c * (qn + hv * hv / qn)
+        rh, rq = 1.0 / hf, 1.0 / qn
+        jhx = (7.0 / 3.0) * c * qn * hu * rh
+        jhy = (7.0 / 3.0) * c * qn * hv * rh
+        jxx = -c * (qn + hu * hu * rq)
+        jxy = -c * hu * hv * rq
+        jyy = -c * (qn + hv * hv * rq)
         m11 = 1.0 - 0.5 * dt * jxx
         m12 = -0.5 * dt * jxy
         m22 = 1.0 - 0.5 * dt * jyy
         rx = dt * (bx + sfx) + 0.5 * dt * jhx * dh
         ry = dt * (by + sfy) + 0.5 * dt * jhy * dh
         det = m11 * m22 - m12 * m12
-        dqx = _w(fric, (rx * m22 - m12 * ry) / det, dt * bx)
-        dqy = _w(fric, (m11 * ry - m12 * rx) / det, dt * by)
+        rd = 1.0 / det
+        dqx = _w(fric, (rx * m22 - m12 * ry) * rd, dt * bx)
+        dqy = _w(fric, (m11 * ry - m12 * rx) * rd, dt * by)
         hn, hun, hvn = h + dh, hu + dqx, hv + dqy
         hn = _w(hn < 0.0, 0 * hn, hn)
         dry = hn <= h_dry

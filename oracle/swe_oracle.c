@@ -11,8 +11,18 @@
  *
  * Every function names the passage of the paper it follows. Where the paper
  * is silent, ambiguous or garbled, the comment says "reading:" and states the
- * interpretation taken. Pins of each function are in tests/test_oracle_*.py;
- * the wall under impinging flow and the fixed-depth / fixed-stage ghosts,
+ * interpretation taken.
+ *
+ * reading (rounding order, which the paper leaves open): a quotient by one
+ * denominator that a formula uses more than once (the cell area of eq. 37,
+ * the depth in the velocities and in the friction Jacobian of eq. 35, |q|,
+ * the determinant of the 2x2 solve, S_R - S_L in the star flux of eq. 18)
+ * is evaluated as one correctly rounded reciprocal and products. Equal in
+ * exact arithmetic to the divisions as printed; one division instead of
+ * several.
+ *
+ * Pins of each function are in tests/test_oracle_*.py; the wall under
+ * impinging flow and the fixed-depth / fixed-stage ghosts,
  * which have no closed form, are pinned by balance laws and by equivalent
  * interior edges.
  *
@@ -190,9 +200,11 @@ void ora_hllc(double g, double h_dry, double hL, double uL, double vL,
     } else if (SR <= 0.0) {
         G[0] = FR[0]; G[1] = FR[1]; G[2] = FR[2];
     } else {
-        G[0] = (SR * FL[0] - SL * FR[0] + SR * SL * (hR - hL)) / (SR - SL);
+        /* one reciprocal of S_R - S_L for both components (header) */
+        double rS = 1.0 / (SR - SL);
+        G[0] = (SR * FL[0] - SL * FR[0] + SR * SL * (hR - hL)) * rS;
         G[1] = (SR * FL[1] - SL * FR[1] + SR * SL * (hR * uR - hL * uL))
-             / (SR - SL);
+             * rS;
         G[2] = G[0] * (Ss >= 0.0 ? vL : vR);
     }
 }
@@ -208,7 +220,8 @@ static void rotate_back(const double G[3], double nx, double ny, double F[3])
 static void velocity(double h_dry, double h, double hu, double hv,
                      double *u, double *v)
 {
-    if (h > h_dry) { *u = hu / h; *v = hv / h; }
+    /* one reciprocal of h for both velocities (header) */
+    if (h > h_dry) { double r = 1.0 / h; *u = hu * r; *v = hv * r; }
     else { *u = 0.0; *v = 0.0; }
 }
 
@@ -324,25 +337,30 @@ void ora_cell_update(double g, double h_dry, double dt, double A,
                      double h, double hu, double hv, double m,
                      const double R[3], double out[3], double *clamp)
 {
-    double bh = R[0] / A, bx = R[1] / A, by = R[2] / A;
+    /* each denominator used several times (|Omega_i|, h, |q|, the
+     * determinant) is inverted once (header) */
+    double rA = 1.0 / A;
+    double bh = R[0] * rA, bx = R[1] * rA, by = R[2] * rA;
     double dh = dt * bh, dqx, dqy;
     double qn = sqrt(hu * hu + hv * hv);
     if (h > h_dry && qn > 0.0) {
         double c = g * m * m / (h * h * cbrt(h));
         double sfx = -c * qn * hu, sfy = -c * qn * hv;
-        double jhx = (7.0 / 3.0) * c * qn * hu / h;
-        double jhy = (7.0 / 3.0) * c * qn * hv / h;
-        double jxx = -c * (qn + hu * hu / qn);
-        double jxy = -c * hu * hv / qn;
-        double jyy = -c * (qn + hv * hv / qn);
+        double rh = 1.0 / h, rq = 1.0 / qn;
+        double jhx = (7.0 / 3.0) * c * qn * hu * rh;
+        double jhy = (7.0 / 3.0) * c * qn * hv * rh;
+        double jxx = -c * (qn + hu * hu * rq);
+        double jxy = -c * hu * hv * rq;
+        double jyy = -c * (qn + hv * hv * rq);
         double m11 = 1.0 - 0.5 * dt * jxx;
         double m12 = -0.5 * dt * jxy;
         double m22 = 1.0 - 0.5 * dt * jyy;
         double rx = dt * (bx + sfx) + 0.5 * dt * jhx * dh;
         double ry = dt * (by + sfy) + 0.5 * dt * jhy * dh;
         double det = m11 * m22 - m12 * m12;
-        dqx = (rx * m22 - m12 * ry) / det;
-        dqy = (m11 * ry - m12 * rx) / det;
+        double rd = 1.0 / det;
+        dqx = (rx * m22 - m12 * ry) * rd;
+        dqy = (m11 * ry - m12 * rx) * rd;
     } else {
         dqx = dt * bx;
         dqy = dt * by;
@@ -728,7 +746,8 @@ double ora_min_rs(const ora *o)
     for (int64_t i = 0; i < o->nc; ++i) {
         double h = o->h[i];
         if (h > h_dry) {
-            double u = o->hu[i] / h, v = o->hv[i] / h;
+            double rh = 1.0 / h;
+            double u = o->hu[i] * rh, v = o->hv[i] * rh;
             double s = sqrt(g * h) + sqrt(u * u + v * v);
             double r = o->inr[i] / s;
             if (r < m) m = r;

@@ -114,8 +114,9 @@ __device__ void hllc_rev(double g, double h_dry, double hL, double uL,
         const double FL1 = qL * uL + 0.5 * g * hL * hL;
         const double FR1 = qR * uR + 0.5 * g * hR * hR;
         const double D = SR - SL;
-        const double G0 = (SR * qL - SL * qR + SR * SL * (hR - hL)) / D;
-        const double G1 = (SR * FL1 - SL * FR1 + SR * SL * (qR - qL)) / D;
+        const double rD = 1.0 / D;   // as the forward step
+        const double G0 = (SR * qL - SL * qR + SR * SL * (hR - hL)) * rD;
+        const double G1 = (SR * FL1 - SL * FR1 + SR * SL * (qR - qL)) * rD;
         // G2 = G0 v*, v* = vL if S* >= 0 else vR
         const bool up = Ss >= 0.0;
         const double G0b = Gb0 + Gb2 * (up ? vL : vR);
@@ -344,7 +345,10 @@ __device__ void cell_update_rev(double h_dry, double dt, double A,
                                 double &hub, double &hvb, double &R0b,
                                 double &R1b, double &R2b, double &gm2b)
 {
-    const double bh = R0 / A, bx = R1 / A, by = R2 / A;
+    // the forward values as the step computes them (one reciprocal per
+    // repeated denominator)
+    const double rA = 1.0 / A;
+    const double bh = R0 * rA, bx = R1 * rA, by = R2 * rA;
     const double dh = dt * bh;
     const double qn = sqrt(hu * hu + hv * hv);
     const bool fric = h > h_dry && qn > 0.0;
@@ -355,19 +359,21 @@ __device__ void cell_update_rev(double h_dry, double dt, double A,
         K = h * h * cbrt(h);
         c = gm2 / K;
         const double sfx = -c * qn * hu, sfy = -c * qn * hv;
-        jhx = (7.0 / 3.0) * c * qn * hu / h;
-        jhy = (7.0 / 3.0) * c * qn * hv / h;
-        const double jxx = -c * (qn + hu * hu / qn);
-        const double jxy = -c * hu * hv / qn;
-        const double jyy = -c * (qn + hv * hv / qn);
+        const double rh = 1.0 / h, rq = 1.0 / qn;
+        jhx = (7.0 / 3.0) * c * qn * hu * rh;
+        jhy = (7.0 / 3.0) * c * qn * hv * rh;
+        const double jxx = -c * (qn + hu * hu * rq);
+        const double jxy = -c * hu * hv * rq;
+        const double jyy = -c * (qn + hv * hv * rq);
         m11 = 1.0 - 0.5 * dt * jxx;
         m12 = -0.5 * dt * jxy;
         m22 = 1.0 - 0.5 * dt * jyy;
         rx = dt * (bx + sfx) + 0.5 * dt * jhx * dh;
         ry = dt * (by + sfy) + 0.5 * dt * jhy * dh;
         det = m11 * m22 - m12 * m12;
-        dqx = (rx * m22 - m12 * ry) / det;
-        dqy = (m11 * ry - m12 * rx) / det;
+        const double rd = 1.0 / det;
+        dqx = (rx * m22 - m12 * ry) * rd;
+        dqy = (m11 * ry - m12 * rx) * rd;
     } else {
         dqx = dt * bx;
         dqy = dt * by;
@@ -455,8 +461,9 @@ __device__ __forceinline__ CellState cell_at(const AdjArgs &a, int c)
     s.u = 0.0;
     s.v = 0.0;
     if (s.h > a.h_dry) {
-        s.u = a.hu[c] / s.h;
-        s.v = a.hv[c] / s.h;
+        const double r = 1.0 / s.h;
+        s.u = a.hu[c] * r;
+        s.v = a.hv[c] * r;
     }
     return s;
 }

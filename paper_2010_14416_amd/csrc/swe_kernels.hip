@@ -52,8 +52,9 @@ __device__ __forceinline__ CellState load_cell(const StepArgs &a, int c)
     const double hu = a.hu0[c], hv = a.hv0[c];
     s.z = a.z[c];
     if (s.h > a.h_dry) {
-        s.u = hu / s.h;
-        s.v = hv / s.h;
+        const double r = 1.0 / s.h;
+        s.u = hu * r;
+        s.v = hv * r;
     } else {
         s.u = 0.0;
         s.v = 0.0;
@@ -370,8 +371,9 @@ void swe_step_kernel(StepArgs a)
         X.u = 0.0;
         X.v = 0.0;
         if (xh > h_dry) {
-            X.u = xhu / xh;
-            X.v = xhv / xh;
+            const double r = 1.0 / xh;
+            X.u = xhu * r;
+            X.v = xhv * r;
         }
     }
     const StepTime st = step_time(a, cw, t_end);
@@ -381,8 +383,9 @@ void swe_step_kernel(StepArgs a)
         s_h[tid] = h;
         s_z[tid] = zc;
         if (h > h_dry) {
-            s_u[tid] = hu / h;
-            s_v[tid] = hv / h;
+            const double r = 1.0 / h;
+            s_u[tid] = hu * r;
+            s_v[tid] = hv * r;
         } else {
             s_u[tid] = 0.0;
             s_v[tid] = 0.0;
@@ -526,7 +529,8 @@ void swe_step_kernel(StepArgs a)
         }
         if (!isfinite(hn) || !isfinite(hun) || !isfinite(hvn)) bad = 1u;
         if (hn > h_dry) {
-            const double u = hun / hn, v = hvn / hn;
+            const double r = 1.0 / hn;
+            const double u = hun * r, v = hvn * r;
             rs = inr / (sqrt(g * hn) + sqrt(u * u + v * v));
         }
     }
@@ -638,7 +642,8 @@ __global__ __launch_bounds__(256) void min_rs_kernel(
          k += int64_t(gridDim.x) * blockDim.x) {
         const double hk = h[k];
         if (hk > h_dry) {
-            const double u = hu[k] / hk, v = hv[k] / hk;
+            const double r = 1.0 / hk;
+            const double u = hu[k] * r, v = hv[k] * r;
             rs = fmin(rs, inr[k] / (sqrt(g * hk) + sqrt(u * u + v * v)));
         }
     }

@@ -72,8 +72,9 @@ __device__ __forceinline__ void hllc(double g, double h_dry, double hL,
     } else {
         const double FL1 = qL * uL + 0.5 * g * hL * hL;
         const double FR1 = qR * uR + 0.5 * g * hR * hR;
-        G0 = (SR * qL - SL * qR + SR * SL * (hR - hL)) / (SR - SL);
-        G1 = (SR * FL1 - SL * FR1 + SR * SL * (qR - qL)) / (SR - SL);
+        const double rS = 1.0 / (SR - SL);
+        G0 = (SR * qL - SL * qR + SR * SL * (hR - hL)) * rS;
+        G1 = (SR * FL1 - SL * FR1 + SR * SL * (qR - qL)) * rS;
         G2 = G0 * (Ss >= 0.0 ? vL : vR);
     }
 }
@@ -179,7 +180,8 @@ __device__ __forceinline__ void cell_update(double h_dry, double dt, double A,
                                             double R2, double &hn, double &hun,
                                             double &hvn, double &clamp)
 {
-    const double bh = R0 / A, bx = R1 / A, by = R2 / A;
+    const double rA = 1.0 / A;
+    const double bh = R0 * rA, bx = R1 * rA, by = R2 * rA;
     const double dh = dt * bh;
     const double qn = sqrt(hu * hu + hv * hv);
     double dqx, dqy;
@@ -188,19 +190,21 @@ __device__ __forceinline__ void cell_update(double h_dry, double dt, double A,
         // (I - dt/2 dS/dq) dq = dt (R_q/A + S_f) + dt/2 (dS/dh) dh
         const double c = gm2 / (h * h * cbrt(h));
         const double sfx = -c * qn * hu, sfy = -c * qn * hv;
-        const double jhx = (7.0 / 3.0) * c * qn * hu / h;
-        const double jhy = (7.0 / 3.0) * c * qn * hv / h;
-        const double jxx = -c * (qn + hu * hu / qn);
-        const double jxy = -c * hu * hv / qn;
-        const double jyy = -c * (qn + hv * hv / qn);
+        const double rh = 1.0 / h, rq = 1.0 / qn;
+        const double jhx = (7.0 / 3.0) * c * qn * hu * rh;
+        const double jhy = (7.0 / 3.0) * c * qn * hv * rh;
+        const double jxx = -c * (qn + hu * hu * rq);
+        const double jxy = -c * hu * hv * rq;
+        const double jyy = -c * (qn + hv * hv * rq);
         const double m11 = 1.0 - 0.5 * dt * jxx;
         const double m12 = -0.5 * dt * jxy;
         const double m22 = 1.0 - 0.5 * dt * jyy;
         const double rx = dt * (bx + sfx) + 0.5 * dt * jhx * dh;
         const double ry = dt * (by + sfy) + 0.5 * dt * jhy * dh;
         const double det = m11 * m22 - m12 * m12;
-        dqx = (rx * m22 - m12 * ry) / det;
-        dqy = (m11 * ry - m12 * rx) / det;
+        const double rd = 1.0 / det;
+        dqx = (rx * m22 - m12 * ry) * rd;
+        dqy = (m11 * ry - m12 * rx) * rd;
     } else {
         dqx = dt * bx;
         dqy = dt * by;

@@ -45,8 +45,8 @@ PLANTED = {
     # eq. 26, right-dry line with the rarefaction speed of a wet side
     "dry_front_speed": ("*SR = uL + 2.0 * aL;", "*SR = uL + aL;"),
     # eq. 35 with the exponent of eq. 5 (4/3) instead of 7/3
-    "jacobian_exponent": ("double jhx = (7.0 / 3.0) * c * qn * hu / h;",
-                          "double jhx = (4.0 / 3.0) * c * qn * hu / h;"),
+    "jacobian_exponent": ("double jhx = (7.0 / 3.0) * c * qn * hu * rh;",
+                          "double jhx = (4.0 / 3.0) * c * qn * hu * rh;"),
     # friction fully explicit (no [I - dt/2 J]^-1)
     "explicit_friction": ("double m11 = 1.0 - 0.5 * dt * jxx;",
                           "double m11 = 1.0;"),
