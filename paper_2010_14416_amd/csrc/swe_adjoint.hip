@@ -121,8 +121,8 @@ __device__ void hllc_rev(double g, double h_dry, double hL, double uL,
         const bool up = Ss >= 0.0;
         const double G0b = Gb0 + Gb2 * (up ? vL : vR);
         if (up) vLb += Gb2 * G0; else vRb += Gb2 * G0;
-        const double N0b = G0b / D, N1b = Gb1 / D;
-        const double Db = -(G0b * G0 + Gb1 * G1) / D;
+        const double N0b = G0b * rD, N1b = Gb1 * rD;
+        const double Db = -(G0b * G0 + Gb1 * G1) * rD;
         SRb += Db;
         SLb -= Db;
         SRb += N0b * (qL + SL * (hR - hL));
@@ -164,15 +164,17 @@ __device__ void hllc_rev(double g, double h_dry, double hL, double uL,
         const double pRb = SRb * aR;
         double hsb = 0.0;
         if (shL) {   // pL = sqrt(wL) / hL, wL = hs (hs + hL) / 2
-            const double sLb = pLb / hL;
-            hLb -= pLb * pL / hL;
+            const double rL = 1.0 / hL;
+            const double sLb = pLb * rL;
+            hLb -= pLb * pL * rL;
             const double wLb = sLb / (2.0 * sL);
             hsb += wLb * (2.0 * hs + hL) / 2.0;
             hLb += wLb * hs / 2.0;
         }
         if (shR) {
-            const double sRb = pRb / hR;
-            hRb -= pRb * pR / hR;
+            const double rR = 1.0 / hR;
+            const double sRb = pRb * rR;
+            hRb -= pRb * pR * rR;
             const double wRb = sRb / (2.0 * sR);
             hsb += wRb * (2.0 * hs + hR) / 2.0;
             hRb += wRb * hs / 2.0;
@@ -187,7 +189,8 @@ __device__ void hllc_rev(double g, double h_dry, double hL, double uL,
             }
         } else {     // hs = (hL gL + hR gR + uL - uR) / (gL + gR)
             const double den = gL + gR;
-            const double nb = hsb / den, denb = -hsb * hs / den;
+            const double rden = 1.0 / den;
+            const double nb = hsb * rden, denb = -hsb * hs * rden;
             hLb += nb * gL;
             hRb += nb * gR;
             uLb += nb;
@@ -196,15 +199,17 @@ __device__ void hllc_rev(double g, double h_dry, double hL, double uL,
             // g_k = sqrt(y_k), y_k = g (h0 + h_k) / (2 h0 h_k)
             const double yLb = gLb / (2.0 * gL), yRb = gRb / (2.0 * gR);
             const double dL = 2.0 * h0 * hL, dR = 2.0 * h0 * hR;
-            double h0b = yLb * (g - yL * 2.0 * hL) / dL +
-                         yRb * (g - yR * 2.0 * hR) / dR;
-            hLb += yLb * (g - yL * 2.0 * h0) / dL;
-            hRb += yRb * (g - yR * 2.0 * h0) / dR;
+            const double rdL = 1.0 / dL, rdR = 1.0 / dR;
+            double h0b = yLb * (g - yL * 2.0 * hL) * rdL +
+                         yRb * (g - yR * 2.0 * hR) * rdR;
+            hLb += yLb * (g - yL * 2.0 * h0) * rdL;
+            hRb += yRb * (g - yR * 2.0 * h0) * rdR;
             // h0 = hsum / 2 - (uR - uL) hsum / c4, c4 = 4 (aL + aR)
             const double du = uR - uL;
-            const double hsumb = h0b * (0.5 - du / c4);
-            const double dub = -h0b * hsum / c4;
-            const double c4b = h0b * du * hsum / (c4 * c4);
+            const double rc4 = 1.0 / c4;
+            const double hsumb = h0b * (0.5 - du * rc4);
+            const double dub = -h0b * hsum * rc4;
+            const double c4b = h0b * du * hsum * rc4 * rc4;
             hLb += hsumb;
             hRb += hsumb;
             uRb += dub;
@@ -235,9 +240,10 @@ __device__ __forceinline__ SideAdj to_conservative(double h_dry,
     r.hv = 0.0;
     r.z = zb;
     if (s.h > h_dry) {
-        r.hu = ub / s.h;
-        r.hv = vb / s.h;
-        r.h -= (ub * s.u + vb * s.v) / s.h;
+        const double rh = 1.0 / s.h;
+        r.hu = ub * rh;
+        r.hv = vb * rh;
+        r.h -= (ub * s.u + vb * s.v) * rh;
     }
     return r;
 }
@@ -355,11 +361,13 @@ __device__ void cell_update_rev(double h_dry, double dt, double A,
     double dqx, dqy;
     double c = 0.0, K = 0.0, jhx = 0.0, jhy = 0.0, m11 = 0.0, m12 = 0.0;
     double m22 = 0.0, rx = 0.0, ry = 0.0, det = 0.0;
+    double rh = 0.0, rq = 0.0, rd = 0.0;   // 1/h, 1/|q|, 1/det
     if (fric) {
         K = h * h * cbrt(h);
         c = gm2 / K;
         const double sfx = -c * qn * hu, sfy = -c * qn * hv;
-        const double rh = 1.0 / h, rq = 1.0 / qn;
+        rh = 1.0 / h;
+        rq = 1.0 / qn;
         jhx = (7.0 / 3.0) * c * qn * hu * rh;
         jhy = (7.0 / 3.0) * c * qn * hv * rh;
         const double jxx = -c * (qn + hu * hu * rq);
@@ -371,7 +379,7 @@ __device__ void cell_update_rev(double h_dry, double dt, double A,
         rx = dt * (bx + sfx) + 0.5 * dt * jhx * dh;
         ry = dt * (by + sfy) + 0.5 * dt * jhy * dh;
         det = m11 * m22 - m12 * m12;
-        const double rd = 1.0 / det;
+        rd = 1.0 / det;
         dqx = (rx * m22 - m12 * ry) * rd;
         dqy = (m11 * ry - m12 * rx) * rd;
     } else {
@@ -394,11 +402,11 @@ __device__ void cell_update_rev(double h_dry, double dt, double A,
     double bxb, byb;
     gm2b = 0.0;
     if (fric) {
-        const double rxb = (dqxb * m22 - dqyb * m12) / det;
-        const double ryb = (-dqxb * m12 + dqyb * m11) / det;
-        double m22b = dqxb * rx / det, m11b = dqyb * ry / det;
-        double m12b = -(dqxb * ry + dqyb * rx) / det;
-        const double detb = -(dqxb * dqx + dqyb * dqy) / det;
+        const double rxb = (dqxb * m22 - dqyb * m12) * rd;
+        const double ryb = (-dqxb * m12 + dqyb * m11) * rd;
+        double m22b = dqxb * rx * rd, m11b = dqyb * ry * rd;
+        double m12b = -(dqxb * ry + dqyb * rx) * rd;
+        const double detb = -(dqxb * dqx + dqyb * dqy) * rd;
         m11b += detb * m22;
         m22b += detb * m11;
         m12b += -2.0 * detb * m12;
@@ -414,24 +422,25 @@ __device__ void cell_update_rev(double h_dry, double dt, double A,
         const double jxyb = -0.5 * dt * m12b;
         const double jyyb = -0.5 * dt * m22b;
         double cb = 0.0, qnb = 0.0;
-        cb += -jxxb * (qn + hu * hu / qn);
-        qnb += -jxxb * c * (1.0 - hu * hu / (qn * qn));
-        hub += -jxxb * c * 2.0 * hu / qn;
-        cb += -jxyb * hu * hv / qn;
-        hub += -jxyb * c * hv / qn;
-        hvb += -jxyb * c * hu / qn;
-        qnb += jxyb * c * hu * hv / (qn * qn);
-        cb += -jyyb * (qn + hv * hv / qn);
-        qnb += -jyyb * c * (1.0 - hv * hv / (qn * qn));
-        hvb += -jyyb * c * 2.0 * hv / qn;
-        cb += jhxb * (7.0 / 3.0) * qn * hu / h;
-        qnb += jhxb * (7.0 / 3.0) * c * hu / h;
-        hub += jhxb * (7.0 / 3.0) * c * qn / h;
-        hb -= jhxb * jhx / h;
-        cb += jhyb * (7.0 / 3.0) * qn * hv / h;
-        qnb += jhyb * (7.0 / 3.0) * c * hv / h;
-        hvb += jhyb * (7.0 / 3.0) * c * qn / h;
-        hb -= jhyb * jhy / h;
+        const double rq2 = rq * rq;
+        cb += -jxxb * (qn + hu * hu * rq);
+        qnb += -jxxb * c * (1.0 - hu * hu * rq2);
+        hub += -jxxb * c * 2.0 * hu * rq;
+        cb += -jxyb * hu * hv * rq;
+        hub += -jxyb * c * hv * rq;
+        hvb += -jxyb * c * hu * rq;
+        qnb += jxyb * c * hu * hv * rq2;
+        cb += -jyyb * (qn + hv * hv * rq);
+        qnb += -jyyb * c * (1.0 - hv * hv * rq2);
+        hvb += -jyyb * c * 2.0 * hv * rq;
+        cb += jhxb * (7.0 / 3.0) * qn * hu * rh;
+        qnb += jhxb * (7.0 / 3.0) * c * hu * rh;
+        hub += jhxb * (7.0 / 3.0) * c * qn * rh;
+        hb -= jhxb * jhx * rh;
+        cb += jhyb * (7.0 / 3.0) * qn * hv * rh;
+        qnb += jhyb * (7.0 / 3.0) * c * hv * rh;
+        hvb += jhyb * (7.0 / 3.0) * c * qn * rh;
+        hb -= jhyb * jhy * rh;
         cb -= sfxb * qn * hu;
         qnb -= sfxb * c * hu;
         hub -= sfxb * c * qn;
@@ -440,17 +449,17 @@ __device__ void cell_update_rev(double h_dry, double dt, double A,
         hvb -= sfyb * c * qn;
         // c = gm2 / (h^2 cbrt(h)): dc/dgm2 = 1 / K, dc/dh = -(7/3) c / h
         gm2b = cb / K;
-        hb += cb * (-(7.0 / 3.0) * c / h);
-        hub += qnb * hu / qn;
-        hvb += qnb * hv / qn;
+        hb += cb * (-(7.0 / 3.0) * c * rh);
+        hub += qnb * hu * rq;
+        hvb += qnb * hv * rq;
     } else {
         bxb = dt * dqxb;
         byb = dt * dqyb;
     }
     const double bhb = dt * dhb;
-    R0b = bhb / A;
-    R1b = bxb / A;
-    R2b = byb / A;
+    R0b = bhb * rA;
+    R1b = bxb * rA;
+    R2b = byb * rA;
 }
 
 __device__ __forceinline__ CellState cell_at(const AdjArgs &a, int c)
