@@ -610,7 +610,10 @@ def run_main(args):
         value=value, ms_per_step=ms_per_step,
         config=dict(workload=desc, n_cells=n, n_edges=info["n_edges"],
                     block_cells=info["block_cells"],
-                    block_threads=args.block_threads or info["block_cells"],
+                    block_threads=args.block_threads or (
+                        2 * info["block_cells"]
+                        if info["n_blocks"] < 256 and info["block_cells"] <= 512
+                        else info["block_cells"]),
                     graph_steps=args.graph_steps,
                     setup_s=round(setup_s, 2),
                     timed_steps=f"{1 + args.warmup}..{done - 1}",
