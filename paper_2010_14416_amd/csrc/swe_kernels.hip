@@ -172,13 +172,29 @@ __device__ __forceinline__ double read_lane(double v, int lane)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// v from the lane that the DPP control CTRL selects within each row of 16
+// (0 where there is none); the lanes of the wave are all active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = unsigned(__builtin_amdgcn_mov_dpp(int(b), CTRL, 0xf, 0xf, true));
+    const unsigned hi = unsigned(__builtin_amdgcn_mov_dpp(int(b >> 32), CTRL, 0xf, 0xf, true));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ StepTime step_time(const StepArgs &a, double word,
                                               double t_end)
 {
+    static_assert(kClockLanes == 8, "the lane minimum combines 8 lanes");
     StepTime st;
-    double mrs = read_lane(word, 0);
-#pragma unroll
-    for (int x = 1; x < kClockLanes; ++x) mrs = fmin(mrs, read_lane(word, x));
+    // minimum of lanes 0..7 into lane 0 in vector registers: swap neighbours
+    // (quad_perm 1,0,3,2), then pairs (quad_perm 2,3,0,1), then lane 4 into
+    // lane 0 (row_shl 4); the minimum of non-negative words takes no order
+    double m = fmin(word, dpp_double<0xB1>(word));
+    m = fmin(m, dpp_double<0x4E>(m));
+    m = fmin(m, dpp_double<0x104>(m));
+    const double mrs = read_lane(m, 0);
     const double t = read_lane(word, kClockLanes);
     st.idx = __double_as_longlong(read_lane(word, kClockLanes + 1));
     st.dt = fmin(a.cfl * mrs, a.dt_max);
