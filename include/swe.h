@@ -156,7 +156,9 @@ swe_status swe_get_params(const swe_ctx *ctx, swe_params *p);
  * Errors: SWE_EMESH for a node index out of range, a repeated vertex, a
  * zero-area triangle, an edge shared by more than two triangles, two
  * triangles on the same side of an edge, a segment that is not a boundary
- * edge or is listed twice, a tag out of range, a non-finite coordinate.
+ * edge or is listed twice, a tag out of range, a non-finite coordinate, a
+ * mesh of 2^29 cells or more (the step addresses its per-cell arrays with
+ * 32-bit byte offsets).
  * Resets the bathymetry and Manning field to 0, the state to dry, the clock
  * to t = 0 and drops any bound workspace. */
 swe_status swe_set_mesh(swe_ctx *ctx, int64_t n_nodes, const double *xy,
@@ -394,7 +396,9 @@ swe_status swe_get_envelope(swe_ctx *ctx, double *h_max, double *t_wet,
  * its results are bitwise those of advancing its context alone.
  *
  * swe_ens_create: members must share g, cfl, h_dry, dt_max, block_cells and
- * the device (SWE_EINVAL), and have a mesh (SWE_ENOTREADY). Copies what it
+ * the device (SWE_EINVAL), and have a mesh (SWE_ENOTREADY); together they
+ * hold fewer than 2^29 cells (each member padded to whole blocks) and 2^30
+ * block-edge records (SWE_EINVAL). Copies what it
  * needs; nothing is retained. The member's monitors are not kept.
  * Errors of a failed create: swe_ens_last_error(NULL).
  * swe_ens_advance: `steps` steps of every member; t_end[n_members] (NULL:

@@ -289,10 +289,12 @@ swe_status swe_ens_create(swe_ens **out, swe_ctx *const *members,
         recs += int64_t(M.be_a.size());
         slots += int64_t(M.bnd_tag.size());
     }
-    if (cells >= (int64_t(1) << 30) || slots >= (int64_t(1) << 30) ||
-        recs >= (int64_t(1) << 31)) {
+    // the step addresses its arrays with 32-bit byte offsets
+    if (cells >= (int64_t(1) << 29) || slots >= (int64_t(1) << 30) ||
+        recs >= (int64_t(1) << 30)) {
         delete e;
-        g_ens_create_error = "ensemble too large: at most 2^30 cells";
+        g_ens_create_error = "ensemble too large: fewer than 2^29 cells "
+                             "and 2^30 block-edge records in total";
         return SWE_EINVAL;
     }
     e->total_cells = cells;

@@ -45,12 +45,31 @@ namespace {
 
 constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
 
+// Element i of an array the step reads per lane, addressed as the array's
+// base plus a 32-bit byte offset, so that a load takes the base from
+// scalar registers and one vector offset register, with no 64-bit address
+// arithmetic per lane. Valid while i * sizeof(T) < 2^32: set-up caps a
+// mesh (or an ensemble) below 2^29 cells and 2^30 block-edge records, and
+// the 8-byte edge arrays are read from their block's first record on.
+template <class T>
+__device__ __forceinline__ T &at(T *p, int i)
+{
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(p) +
+                                  uint32_t(i) * uint32_t(sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ const T &at(const T *p, int i)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) +
+                                        uint32_t(i) * uint32_t(sizeof(T)));
+}
+
 __device__ __forceinline__ CellState load_cell(const StepArgs &a, int c)
 {
     CellState s;
-    s.h = a.h0[c];
-    const double hu = a.hu0[c], hv = a.hv0[c];
-    s.z = a.z[c];
+    s.h = at(a.h0, c);
+    const double hu = at(a.hu0, c), hv = at(a.hv0, c);
+    s.z = at(a.z, c);
     if (s.h > a.h_dry) {
         const double r = 1.0 / s.h;
         s.u = hu * r;
@@ -305,9 +324,9 @@ void swe_step_kernel(StepArgs a)
         if (SLOT && tid < NC && blk * NC + tid < cell_end) {
             // a fresh output slot: carry the unchanged state over
             const int c = blk * NC + tid;
-            a.h1[c] = a.h0[c];
-            a.hu1[c] = a.hu0[c];
-            a.hv1[c] = a.hv0[c];
+            at(a.h1, c) = at(a.h0, c);
+            at(a.hu1, c) = at(a.hu0, c);
+            at(a.hv1, c) = at(a.hv0, c);
             if (a.r_out) {
                 a.r_out[c] = 0.0;
                 a.r_out[a.n_cells + c] = 0.0;
@@ -336,24 +355,24 @@ void swe_step_kernel(StepArgs a)
         bnd = *reinterpret_cast<const int4 *>(a.mon->blk_bnd + 4 * blk);
     double h = 0.0, hu = 0.0, hv = 0.0, zc = 0.0;
     if (tid < NC && tid < nc_read) {
-        h = a.h0[i];
-        zc = a.z[i];
+        h = at(a.h0, i);
+        zc = at(a.z, i);
     }
     const double cw = clock_word(a, clock);
     int32_t ea = 0, eb = 0, ea2 = 0, eb2 = 0;
     double nx = 0.0, ny = 0.0, len = 0.0;
     if (tid < ne) {
-        ea = a.be_a[e0 + tid];
-        eb = a.be_b[e0 + tid];
+        ea = at(a.be_a, e0 + tid);
+        eb = at(a.be_b, e0 + tid);
         if (EAGER) {
-            nx = a.be_nx[e0 + tid];
-            ny = a.be_ny[e0 + tid];
-            len = a.be_len[e0 + tid];
+            nx = at(a.be_nx + e0, tid);
+            ny = at(a.be_ny + e0, tid);
+            len = at(a.be_len + e0, tid);
         }
     }
     if (tid + NT < ne) {              // the thread's second edge record
-        ea2 = a.be_a[e0 + tid + NT];
-        eb2 = a.be_b[e0 + tid + NT];
+        ea2 = at(a.be_a, e0 + tid + NT);
+        eb2 = at(a.be_b, e0 + tid + NT);
     }
     unsigned long long act_prev = 0ull;   // to s_act with phase 1
     if (tid < NC && (tid & 63) == 0)
@@ -371,16 +390,16 @@ void swe_step_kernel(StepArgs a)
         if (tid < ne && (xa || xb)) {
             const int x = xa ? ea : eb;
             xmark = cross_mark<NC>(ea, eb);
-            xh = a.h0[x];
-            xhu = a.hu0[x];
-            xhv = a.hv0[x];
-            xz = a.z[x];
+            xh = at(a.h0, x);
+            xhu = at(a.hu0, x);
+            xhv = at(a.hv0, x);
+            xz = at(a.z, x);
         }
         // the momentum of a dry cell is read in phase 3, and only if needed
         // (requested after the neighbour state, whose address arrived first)
         if (owner && h > h_dry) {
-            hu = a.hu0[i];
-            hv = a.hv0[i];
+            hu = at(a.hu0, i);
+            hv = at(a.hv0, i);
         }
         X.h = xh;
         X.z = xz;
@@ -445,9 +464,9 @@ void swe_step_kernel(StepArgs a)
         double cr0 = 0.0, cr1 = 0.0, cr2 = 0.0;
         if (!idle) {
             if (!EAGER) {
-                enx = a.be_nx[e0 + k];
-                eny = a.be_ny[e0 + k];
-                elen = a.be_len[e0 + k];
+                enx = at(a.be_nx + e0, k);
+                eny = at(a.be_ny + e0, k);
+                elen = at(a.be_len + e0, k);
             }
             edge_contrib(g, h_dry, pb.kind == 2, bc, Lc, Rc, enx, eny, elen,
                          cl0, cl1, cl2, cr0, cr1, cr2);
@@ -470,16 +489,16 @@ void swe_step_kernel(StepArgs a)
     for (int k = tid + NT; k < ne; k += NT) {   // blocks with > NT edges
         int32_t va = ea2, vb = eb2;
         if (k != tid + NT) {
-            va = a.be_a[e0 + k];
-            vb = a.be_b[e0 + k];
+            va = at(a.be_a, e0 + k);
+            vb = at(a.be_b, e0 + k);
         } else {
             xmark2 = cross_mark<NC>(va, vb);
         }
         double enx = 0.0, eny = 0.0, elen = 0.0;
         if (EAGER) {
-            enx = a.be_nx[e0 + k];
-            eny = a.be_ny[e0 + k];
-            elen = a.be_len[e0 + k];
+            enx = at(a.be_nx + e0, k);
+            eny = at(a.be_ny + e0, k);
+            elen = at(a.be_len + e0, k);
         }
         CellState Y;
         Y.h = 0.0; Y.u = 0.0; Y.v = 0.0; Y.z = 0.0;
@@ -492,9 +511,9 @@ void swe_step_kernel(StepArgs a)
     double area = 0.0, gm2 = 0.0, inr = 0.0;
     const double hc = owner ? s_h[tid] : 0.0;   // h of the owned cell
     if (owner && (EAGER || hc > h_dry)) {
-        area = a.area[i];
-        gm2 = a.gm2[i];
-        inr = a.inradius[i];
+        area = at(a.area, i);
+        gm2 = at(a.gm2, i);
+        inr = at(a.inradius, i);
     }
     __syncthreads();
 
@@ -530,11 +549,11 @@ void swe_step_kernel(StepArgs a)
             active = false;
         } else {
             if (hc <= h_dry) {
-                hu = a.hu0[i];
-                hv = a.hv0[i];
+                hu = at(a.hu0, i);
+                hv = at(a.hv0, i);
                 if (!EAGER) {
-                    area = a.area[i];
-                    inr = a.inradius[i];
+                    area = at(a.area, i);
+                    inr = at(a.inradius, i);
                 }
             }
             hun = hu;
@@ -580,7 +599,8 @@ void swe_step_kernel(StepArgs a)
             // record only if that one reaches another block
             for (int k = tid + 2 * NT; xmark2 != 0xffffffffu && k < ne;
                  k += NT) {
-                const uint32_t m = cross_mark<NC>(a.be_a[e0 + k], a.be_b[e0 + k]);
+                const uint32_t m =
+                    cross_mark<NC>(at(a.be_a, e0 + k), at(a.be_b, e0 + k));
                 if (m == 0xffffffffu) break;
                 mark(m);
             }
@@ -591,9 +611,9 @@ void swe_step_kernel(StepArgs a)
     // in the two previous steps already holds (h, 0, 0) in the output buffer
     // (it held U^{n-1} = U^n).
     if (owner && (active || quiet_steps < 2 || a.store_all || SLOT)) {
-        a.h1[i] = hn;
-        a.hu1[i] = hun;
-        a.hv1[i] = hvn;
+        at(a.h1, i) = hn;
+        at(a.hu1, i) = hun;
+        at(a.hv1, i) = hvn;
     }
     if (MON && owner && hn > hc) {
         // flood envelope: h_max >= h always holds, so the highest depth can
@@ -612,7 +632,7 @@ void swe_step_kernel(StepArgs a)
         // only so that nothing waits for it).
         const int4 b = s_bnd[0];
         for (int k = tid; k < b.z; k += NT) {
-            const Side pa = decode_side(a.be_a[b.y + k]);
+            const Side pa = decode_side(at(a.be_a, b.y + k));
             const double rate = -s_c[pa.k * NC + pa.local];
             a.mon->mon_rate[b.x + k] = rate;
             unsafeAtomicAdd(&a.mon->mon_vol[b.x + k], st.dt * rate);

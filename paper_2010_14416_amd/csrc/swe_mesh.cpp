@@ -620,8 +620,9 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
     //                       only; slots numbered in block order)
     const int32_t B = block_cells;
     const int64_t nblk = (nc + B - 1) / B;
-    if (nc >= (int64_t(1) << 30)) {
-        err = "mesh too large: at most 2^30 cells";
+    // the step addresses its 8-byte cell arrays with 32-bit byte offsets
+    if (nc >= (int64_t(1) << 29)) {
+        err = "mesh too large: fewer than 2^29 cells";
         return false;
     }
     M.block_cells = B;
@@ -680,6 +681,11 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
     }
     M.max_block_edges = emax;
     const int64_t nbe = M.blk_edge[nblk];
+    // and its 4-byte edge-record arrays likewise
+    if (nbe >= (int64_t(1) << 30)) {
+        err = "mesh too large: fewer than 2^30 block-edge records";
+        return false;
+    }
     M.be_a.resize(nbe);
     M.be_b.resize(nbe);
     M.be_nx.resize(nbe);
