@@ -465,14 +465,14 @@ __device__ void cell_update_rev(double h_dry, double dt, double A,
 __device__ __forceinline__ CellState cell_at(const AdjArgs &a, int c)
 {
     CellState s;
-    s.h = a.h[c];
-    s.z = a.z[c];
+    s.h = at(a.h, c);
+    s.z = at(a.z, c);
     s.u = 0.0;
     s.v = 0.0;
     if (s.h > a.h_dry) {
         const double r = 1.0 / s.h;
-        s.u = a.hu[c] * r;
-        s.v = a.hv[c] * r;
+        s.u = at(a.hu, c) * r;
+        s.v = at(a.hv, c) * r;
     }
     return s;
 }
@@ -487,7 +487,7 @@ __device__ __forceinline__ bool dormant_dry(const AdjArgs &a, int blk,
                                            bool owner, int i)
 {
     if (!a.ran || a.ran[blk] != 0) return false;
-    const bool dry = !owner || a.h[i] == 0.0;
+    const bool dry = !owner || at(a.h, i) == 0.0;
     return __syncthreads_and(dry) != 0;
 }
 
@@ -503,13 +503,13 @@ __global__ __launch_bounds__(NC) void adj_cell_kernel(AdjArgs a)
     if (dormant_dry<NC>(a, blk, owner, i)) {
         // what the cell reverse gives for h = 0 and R = 0 (hn = 0 <= h_dry)
         if (owner) {
-            const double lh = a.lam_h[i];
-            a.ld_h[i] = lh;
-            a.ld_hu[i] = 0.0;
-            a.ld_hv[i] = 0.0;
-            a.lr_h[i] = a.dt * lh / a.area[i];
-            a.lr_hu[i] = 0.0;
-            a.lr_hv[i] = 0.0;
+            const double lh = at(a.lam_h, i);
+            at(a.ld_h, i) = lh;
+            at(a.ld_hu, i) = 0.0;
+            at(a.ld_hv, i) = 0.0;
+            at(a.lr_h, i) = a.dt * lh / at(a.area, i);
+            at(a.lr_hu, i) = 0.0;
+            at(a.lr_hv, i) = 0.0;
         }
         return;
     }
@@ -519,12 +519,12 @@ __global__ __launch_bounds__(NC) void adj_cell_kernel(AdjArgs a)
     // list), then the neighbour of the first edge, as in the forward step
     int32_t ea = 0, eb = 0, ea2 = 0, eb2 = 0;
     if (tid < ne) {
-        ea = a.be_a[e0 + tid];
-        eb = a.be_b[e0 + tid];
+        ea = at(a.be_a, e0 + tid);
+        eb = at(a.be_b, e0 + tid);
     }
     if (tid + NC < ne) {
-        ea2 = a.be_a[e0 + tid + NC];
-        eb2 = a.be_b[e0 + tid + NC];
+        ea2 = at(a.be_a, e0 + tid + NC);
+        eb2 = at(a.be_b, e0 + tid + NC);
     }
     if (owner) {
         const CellState s = cell_at(a, i);
@@ -569,8 +569,8 @@ __global__ __launch_bounds__(NC) void adj_cell_kernel(AdjArgs a)
                cr2 = 0.0;
         if (!idle)
             edge_contrib(g, h_dry, pb.kind == 2, bc, Lc, Rc,
-                         a.be_nx[e0 + k], a.be_ny[e0 + k], a.be_len[e0 + k],
-                         cl0, cl1, cl2, cr0, cr1, cr2);
+                         at(a.be_nx + e0, k), at(a.be_ny + e0, k),
+                         at(a.be_len + e0, k), cl0, cl1, cl2, cr0, cr1, cr2);
         if (pa.kind == 0) {
             double *d = s_c + pa.k * NC + pa.local;
             d[0] = cl0;
@@ -588,8 +588,8 @@ __global__ __launch_bounds__(NC) void adj_cell_kernel(AdjArgs a)
     for (int k = tid + NC; k < ne; k += NC) {
         int32_t va = ea2, vb = eb2;
         if (k != tid + NC) {
-            va = a.be_a[e0 + k];
-            vb = a.be_b[e0 + k];
+            va = at(a.be_a, e0 + k);
+            vb = at(a.be_b, e0 + k);
         }
         CellState Y;
         Y.h = 0.0; Y.u = 0.0; Y.v = 0.0; Y.z = 0.0;
@@ -606,18 +606,19 @@ __global__ __launch_bounds__(NC) void adj_cell_kernel(AdjArgs a)
         R1 += s_c[(3 + k) * NC + tid];
         R2 += s_c[(6 + k) * NC + tid];
     }
-    const double h = a.h[i];
+    const double h = at(a.h, i);
     double hb, hub, hvb, R0b, R1b, R2b, gm2b;
-    cell_update_rev(h_dry, a.dt, a.area[i], h > h_dry ? a.gm2[i] : 0.0, h,
-                    a.hu[i], a.hv[i], R0, R1, R2, a.lam_h[i], a.lam_hu[i],
-                    a.lam_hv[i], hb, hub, hvb, R0b, R1b, R2b, gm2b);
-    a.ld_h[i] = hb;
-    a.ld_hu[i] = hub;
-    a.ld_hv[i] = hvb;
-    a.lr_h[i] = R0b;
-    a.lr_hu[i] = R1b;
-    a.lr_hv[i] = R2b;
-    if (gm2b != 0.0) a.grad_gm2[i] += gm2b;
+    cell_update_rev(h_dry, a.dt, at(a.area, i),
+                    h > h_dry ? at(a.gm2, i) : 0.0, h, at(a.hu, i),
+                    at(a.hv, i), R0, R1, R2, at(a.lam_h, i), at(a.lam_hu, i),
+                    at(a.lam_hv, i), hb, hub, hvb, R0b, R1b, R2b, gm2b);
+    at(a.ld_h, i) = hb;
+    at(a.ld_hu, i) = hub;
+    at(a.ld_hv, i) = hvb;
+    at(a.lr_h, i) = R0b;
+    at(a.lr_hu, i) = R1b;
+    at(a.lr_hv, i) = R2b;
+    if (gm2b != 0.0) at(a.grad_gm2, i) += gm2b;
 }
 
 // The cell pass when the forward step stored its summed contributions R:
@@ -633,29 +634,30 @@ __global__ __launch_bounds__(NC) void adj_cell_stored_kernel(AdjArgs a)
     const bool skip = dormant_dry<NC>(a, blk, owner, i);
     if (!owner) return;
     if (skip) {
-        const double lh = a.lam_h[i];
-        a.ld_h[i] = lh;
-        a.ld_hu[i] = 0.0;
-        a.ld_hv[i] = 0.0;
-        a.lr_h[i] = a.dt * lh / a.area[i];
-        a.lr_hu[i] = 0.0;
-        a.lr_hv[i] = 0.0;
+        const double lh = at(a.lam_h, i);
+        at(a.ld_h, i) = lh;
+        at(a.ld_hu, i) = 0.0;
+        at(a.ld_hv, i) = 0.0;
+        at(a.lr_h, i) = a.dt * lh / at(a.area, i);
+        at(a.lr_hu, i) = 0.0;
+        at(a.lr_hv, i) = 0.0;
         return;
     }
     const double R0 = a.R[i], R1 = a.R[a.n_cells + i],
                  R2 = a.R[2 * a.n_cells + i];
-    const double h = a.h[i], h_dry = a.h_dry;
+    const double h = at(a.h, i), h_dry = a.h_dry;
     double hb, hub, hvb, R0b, R1b, R2b, gm2b;
-    cell_update_rev(h_dry, a.dt, a.area[i], h > h_dry ? a.gm2[i] : 0.0, h,
-                    a.hu[i], a.hv[i], R0, R1, R2, a.lam_h[i], a.lam_hu[i],
-                    a.lam_hv[i], hb, hub, hvb, R0b, R1b, R2b, gm2b);
-    a.ld_h[i] = hb;
-    a.ld_hu[i] = hub;
-    a.ld_hv[i] = hvb;
-    a.lr_h[i] = R0b;
-    a.lr_hu[i] = R1b;
-    a.lr_hv[i] = R2b;
-    if (gm2b != 0.0) a.grad_gm2[i] += gm2b;
+    cell_update_rev(h_dry, a.dt, at(a.area, i),
+                    h > h_dry ? at(a.gm2, i) : 0.0, h, at(a.hu, i),
+                    at(a.hv, i), R0, R1, R2, at(a.lam_h, i), at(a.lam_hu, i),
+                    at(a.lam_hv, i), hb, hub, hvb, R0b, R1b, R2b, gm2b);
+    at(a.ld_h, i) = hb;
+    at(a.ld_hu, i) = hub;
+    at(a.ld_hv, i) = hvb;
+    at(a.lr_h, i) = R0b;
+    at(a.lr_hu, i) = R1b;
+    at(a.lr_hv, i) = R2b;
+    if (gm2b != 0.0) at(a.grad_gm2, i) += gm2b;
 }
 
 template <int NC>
@@ -670,9 +672,9 @@ __global__ __launch_bounds__(NC) void adj_edge_kernel(AdjArgs a)
     const int i = c0 + tid;
     if (dormant_dry<NC>(a, blk, owner, i)) {
         if (owner) {
-            a.lam_out_h[i] = a.lam_h[i] + 0.0;
-            a.lam_out_hu[i] = 0.0;
-            a.lam_out_hv[i] = 0.0;
+            at(a.lam_out_h, i) = at(a.lam_h, i) + 0.0;
+            at(a.lam_out_hu, i) = 0.0;
+            at(a.lam_out_hv, i) = 0.0;
         }
         return;
     }
@@ -684,14 +686,14 @@ __global__ __launch_bounds__(NC) void adj_edge_kernel(AdjArgs a)
         s_u[tid] = s.u;
         s_v[tid] = s.v;
         s_z[tid] = s.z;
-        s_r[tid] = a.lr_h[i];
-        s_r[NC + tid] = a.lr_hu[i];
-        s_r[2 * NC + tid] = a.lr_hv[i];
+        s_r[tid] = at(a.lr_h, i);
+        s_r[NC + tid] = at(a.lr_hu, i);
+        s_r[2 * NC + tid] = at(a.lr_hv, i);
     }
     __syncthreads();
     for (int k = tid; k < ne; k += NC) {
-        const Side pa = decode_side(a.be_a[e0 + k]);
-        const Side pb = decode_side(a.be_b[e0 + k]);
+        const Side pa = decode_side(at(a.be_a, e0 + k));
+        const Side pb = decode_side(at(a.be_b, e0 + k));
         CellState Lc, Rc;
         double lb[3], rb[3] = {0.0, 0.0, 0.0};
         if (pa.kind == 0) {
@@ -702,16 +704,17 @@ __global__ __launch_bounds__(NC) void adj_edge_kernel(AdjArgs a)
             lb[2] = s_r[2 * NC + pa.local];
         } else {
             Lc = cell_at(a, pa.global);
-            lb[0] = a.lr_h[pa.global];
-            lb[1] = a.lr_hu[pa.global];
-            lb[2] = a.lr_hv[pa.global];
+            lb[0] = at(a.lr_h, pa.global);
+            lb[1] = at(a.lr_hu, pa.global);
+            lb[2] = at(a.lr_hv, pa.global);
         }
         SideAdj La{0.0, 0.0, 0.0, 0.0}, Ra{0.0, 0.0, 0.0, 0.0};
         if (pb.kind == 2) {
             const BcEntry bc = a.bc[pb.global];
             if (!(Lc.h == 0.0 && (bc.kind == 0 || bc.kind == 1)))
-                boundary_edge_rev(g, h_dry, bc, Lc, a.be_nx[e0 + k],
-                                  a.be_ny[e0 + k], a.be_len[e0 + k], lb, La);
+                boundary_edge_rev(g, h_dry, bc, Lc, at(a.be_nx + e0, k),
+                                  at(a.be_ny + e0, k), at(a.be_len + e0, k),
+                                  lb, La);
         } else {
             if (pb.kind == 0) {
                 Rc.h = s_h[pb.local]; Rc.u = s_u[pb.local];
@@ -721,14 +724,14 @@ __global__ __launch_bounds__(NC) void adj_edge_kernel(AdjArgs a)
                 rb[2] = s_r[2 * NC + pb.local];
             } else {
                 Rc = cell_at(a, pb.global);
-                rb[0] = a.lr_h[pb.global];
-                rb[1] = a.lr_hu[pb.global];
-                rb[2] = a.lr_hv[pb.global];
+                rb[0] = at(a.lr_h, pb.global);
+                rb[1] = at(a.lr_hu, pb.global);
+                rb[2] = at(a.lr_hv, pb.global);
             }
             if (!(Lc.h == 0.0 && Rc.h == 0.0))
-                interior_edge_rev(g, h_dry, Lc, Rc, a.be_nx[e0 + k],
-                                  a.be_ny[e0 + k], a.be_len[e0 + k], lb, rb,
-                                  La, Ra);
+                interior_edge_rev(g, h_dry, Lc, Rc, at(a.be_nx + e0, k),
+                                  at(a.be_ny + e0, k), at(a.be_len + e0, k),
+                                  lb, rb, La, Ra);
         }
         if (pa.kind == 0) {
             double *d = s_a + pa.k * NC + pa.local;
@@ -747,7 +750,8 @@ __global__ __launch_bounds__(NC) void adj_edge_kernel(AdjArgs a)
     }
     __syncthreads();
     if (!owner) return;
-    double lh = a.ld_h[i], lhu = a.ld_hu[i], lhv = a.ld_hv[i], lz = 0.0;
+    double lh = at(a.ld_h, i), lhu = at(a.ld_hu, i), lhv = at(a.ld_hv, i);
+    double lz = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         lh += s_a[k * NC + tid];
@@ -755,10 +759,10 @@ __global__ __launch_bounds__(NC) void adj_edge_kernel(AdjArgs a)
         lhv += s_a[(6 + k) * NC + tid];
         lz += s_a[(9 + k) * NC + tid];
     }
-    a.lam_out_h[i] = lh;
-    a.lam_out_hu[i] = lhu;
-    a.lam_out_hv[i] = lhv;
-    if (lz != 0.0) a.grad_z[i] += lz;
+    at(a.lam_out_h, i) = lh;
+    at(a.lam_out_hu, i) = lhu;
+    at(a.lam_out_hv, i) = lhv;
+    if (lz != 0.0) at(a.grad_z, i) += lz;
 }
 
 __global__ __launch_bounds__(256) void gm2_to_manning_kernel(

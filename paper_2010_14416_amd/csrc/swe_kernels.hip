@@ -45,25 +45,6 @@ namespace {
 
 constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
 
-// Element i of an array the step reads per lane, addressed as the array's
-// base plus a 32-bit byte offset, so that a load takes the base from
-// scalar registers and one vector offset register, with no 64-bit address
-// arithmetic per lane. Valid while i * sizeof(T) < 2^32: set-up caps a
-// mesh (or an ensemble) below 2^29 cells and 2^30 block-edge records, and
-// the 8-byte edge arrays are read from their block's first record on.
-template <class T>
-__device__ __forceinline__ T &at(T *p, int i)
-{
-    return *reinterpret_cast<T *>(reinterpret_cast<char *>(p) +
-                                  uint32_t(i) * uint32_t(sizeof(T)));
-}
-template <class T>
-__device__ __forceinline__ const T &at(const T *p, int i)
-{
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) +
-                                        uint32_t(i) * uint32_t(sizeof(T)));
-}
-
 __device__ __forceinline__ CellState load_cell(const StepArgs &a, int c)
 {
     CellState s;
@@ -197,8 +178,10 @@ template <int CTRL>
 __device__ __forceinline__ double dpp_double(double v)
 {
     const long long b = __double_as_longlong(v);
-    const unsigned lo = unsigned(__builtin_amdgcn_mov_dpp(int(b), CTRL, 0xf, 0xf, true));
-    const unsigned hi = unsigned(__builtin_amdgcn_mov_dpp(int(b >> 32), CTRL, 0xf, 0xf, true));
+    const unsigned lo =
+        unsigned(__builtin_amdgcn_mov_dpp(int(b), CTRL, 0xf, 0xf, true));
+    const unsigned hi =
+        unsigned(__builtin_amdgcn_mov_dpp(int(b >> 32), CTRL, 0xf, 0xf, true));
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 

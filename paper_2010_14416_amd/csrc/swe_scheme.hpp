@@ -1,8 +1,9 @@
 // Device arithmetic of one explicit step shared by the step kernel
 // (swe_kernels.hip) and the adjoint kernels (swe_adjoint.hip): the HLLC flux,
-// the contributions of one edge, the update of one cell, and the decoding of
-// a block-edge record. Every formula is evaluated as written, operation by
-// operation (no contraction: include after `#pragma clang fp contract(off)`).
+// the contributions of one edge, the update of one cell, the decoding of a
+// block-edge record, and the per-lane array addressing. Every formula is
+// evaluated as written, operation by operation (no contraction: include
+// after `#pragma clang fp contract(off)`).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,6 +14,25 @@
 #include "swe_mesh.hpp"
 
 namespace swe {
+
+// Element i of an array read or written per lane, addressed as the array's
+// base plus a 32-bit byte offset, so that a load takes the base from
+// scalar registers and one vector offset register, with no 64-bit address
+// arithmetic per lane. Valid while i * sizeof(T) < 2^32: set-up caps a
+// mesh (or an ensemble) below 2^29 cells and 2^30 block-edge records, and
+// the 8-byte edge arrays are read from their block's first record on.
+template <class T>
+__device__ __forceinline__ T &at(T *p, int i)
+{
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(p) +
+                                  uint32_t(i) * uint32_t(sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ const T &at(const T *p, int i)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) +
+                                        uint32_t(i) * uint32_t(sizeof(T)));
+}
 
 // HLLC flux in the frame of the edge normal (u normal, v tangential).
 // A side at or below h_dry is dry: depth and velocities zero. Wave speeds of
