@@ -228,6 +228,11 @@ bool build_block_mesh(int64_t nn, const double *xy, int64_t nc,
         err = "mesh too large for 32-bit indices";
         return false;
     }
+    // the step addresses its 8-byte cell arrays with 32-bit byte offsets
+    if (nc >= (int64_t(1) << 29)) {
+        err = "mesh too large: fewer than 2^29 cells";
+        return false;
+    }
     for (int64_t k = 0; k < 2 * nn; ++k)
         if (!std::isfinite(xy[k])) {
             err = fmt("node %lld has a non-finite coordinate",

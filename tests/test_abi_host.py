@@ -194,6 +194,21 @@ def test_mesh_errors(ctx, kind):
     assert S.swe_last_error(ctx)
 
 
+def test_mesh_of_2_to_the_29_cells_is_rejected_before_reading_it(ctx):
+    """The step addresses its per-cell arrays with 32-bit byte offsets, so
+    set-up refuses 2^29 cells or more; the count is checked before the
+    triangle array is read (a three-triangle array stands in for it)."""
+    xy, tri = two_triangles()
+    tri3 = np.ascontiguousarray(np.vstack([tri, tri[:1]]), dtype=np.int32)
+    st = S.load().swe_set_mesh(
+        ctx, xy.shape[0], xy.ctypes.data_as(S._pd), 1 << 29,
+        tri3.ctypes.data_as(S._pi32), 0, None, None)
+    assert st == S.SWE_EMESH
+    assert "2^29" in S.swe_last_error(ctx)
+    S.swe_set_mesh(ctx, xy, tri)       # a valid mesh is still accepted
+    assert S.swe_mesh_info(ctx)["n_cells"] == 2
+
+
 def test_calls_before_mesh_are_not_ready(ctx):
     with pytest.raises(S.SweError) as e:
         S.swe_advance(ctx, 1)
