@@ -33,9 +33,10 @@ sys.path.insert(0, ROOT)
 METRIC = ("cell-updates/s FP64 + HBM GB/s vs peak; ensemble and adjoint "
           "cost vs plain")
 PEAK_HBM_GBS = 8000.0           # MI355X HBM3E, published
-# Algorithmic bytes the method moves per cell-update (FP64 state in and
-# out, per-cell bed / friction / 1/area / inscribed radius, ~1.5 edges of
-# geometry and connectivity, per-cell edge slots); derivation in the design doc.
+# Algorithmic bytes the method moves per cell-update in this FP64 / int32
+# layout: U^n in 24 + U^{n+1} out 24 + bed, g m^2, 1/area and inscribed
+# radius 32 + about 1.5 edges x (normal, length 24 + two cell indices 8) 48
+# + per-cell edge references 12.
 ALG_BYTES_PER_CELL = 140
 KERNEL_SRC = [os.path.join(ROOT, "paper_2010_14416_amd", "csrc", f)
               for f in ("swe_kernels.hip", "swe_scheme.hpp", "swe_device.hpp",
