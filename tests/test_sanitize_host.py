@@ -2,7 +2,7 @@
 UndefinedBehaviorSanitizer (g++/gcc, CPU only) and run on small workloads:
 the dam-break canal, a river reach with inflow and a fixed outlet stage, a
 two-triangle mesh, each mesh also given as an edge list, and broken meshes
-that must be refused. A sanitizer finding aborts the driver (no recovery)
+that must be refused. A sanitizer finding aborts the test program (no recovery)
 and fails the test."""
 import os
 import shutil
